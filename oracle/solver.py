@@ -1,0 +1,223 @@
+"""Distributed D-R deblurring solver (Algorithm 1), FP64 reference.
+
+Per tile t the local cost is (Section III-A)
+
+    f_t(x) = 1/2 ||y_t - H_t x||^2_{W_t} + lambda phi(D x) + iota_{>=0}(x).
+
+Algorithm 1 iterates, with metric alpha_t = gamma omega_t (Section III-B):
+
+    x_t  <- prox_{alpha_t^-1, f_t}(u_t)                 (Local-Solver)
+    zbar <- sum_t alpha_t (2 x_t - u_t) / sum_t alpha_t  (the Lemma: weighted
+                                                          average over the
+                                                          tiles covering a pixel)
+    u_t  <- u_t + rho (zbar|_t - x_t)
+
+The Local-Solver is inexact and warm-started from the previous x_t (Section
+IV-B allows any fast method and inexact prox steps).  Here it is projected
+gradient on the prox objective f_t(w) + 1/2 ||w - u_t||^2_{alpha_t}:
+
+    g = H_t^T W_t (H_t w - y_t) + lambda grad phi(w) + alpha_t (w - u_t)
+    w <- max(0, w - tau_t g),
+
+with tau_t = 1/L_t and L_t = max(W_t) max(H_t 1) + lambda L_phi + gamma
+max(omega_t), an upper bound on the Lipschitz constant of the gradient
+(max(H_t 1) is the largest row sum of H_t; its column sums are at most 1 for
+non-negative unit-sum PSFs and tents summing to one, so ||H_t||^2 <= max(H_t 1)).
+
+One "iteration" is one projected-gradient step on every tile; consensus runs
+after every n_inner of them.  The residual is the D-R fixed-point residual
+||u^{k+1} - u^k|| / ||u^{k+1}|| over all tiles.  The output image is
+sum_t omega_t x_t on X.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import prior
+from .operator import DirectOperator
+
+
+@dataclasses.dataclass
+class Problem:
+    layout: object
+    psfs: np.ndarray           # [G_y, G_x, P, P]
+    y: np.ndarray              # observed image [M_y, M_x]
+    W: np.ndarray              # inverse-variance weights [M_y, M_x]
+    lam: float = 1e-3
+    reg: str = "tv"            # "tv" | "huber"
+    reg_param: float = 1e-3    # eps for tv, delta for huber
+    bc: str = "neumann"        # "neumann" | "circular"
+    gamma: float = 0.4
+    rho: float = 1.0
+    positivity: bool = True
+    operator: object = None    # DirectOperator (default) or FFTOperator
+
+    def __post_init__(self):
+        if self.operator is None:
+            self.operator = DirectOperator(self.layout, self.psfs)
+
+    @property
+    def n_tiles(self):
+        return self.layout.n_tiles
+
+    def y_t(self, t):
+        return self.layout.block_of(self.y, t)
+
+    def W_t(self, t):
+        return self.layout.block_of(self.W, t)
+
+    def alpha_t(self, t):
+        return self.gamma * self.layout.omega(t)
+
+    def H(self, t, x):
+        return self.operator.apply_H(t, x)
+
+    def Ht(self, t, s):
+        return self.operator.apply_Ht(t, s)
+
+
+def row_sum_bound(problem, t):
+    """max over B_t of H_t 1 (the largest row sum of H_t)."""
+    ones = np.ones(problem.layout.support_shape(t))
+    return float(np.max(problem.H(t, ones)))
+
+
+def step_size(problem, t):
+    """tau_t = 1 / L_t (see module docstring)."""
+    L = (float(np.max(problem.W_t(t))) * row_sum_bound(problem, t)
+         + problem.lam * prior.lipschitz(problem.reg, problem.reg_param)
+         + float(np.max(problem.alpha_t(t))))
+    return 1.0 / L
+
+
+def prox_objective(problem, t, w, u):
+    """f_t(w) + 1/2 ||w - u||^2_alpha (the Local-Solver's target)."""
+    d = problem.H(t, w) - problem.y_t(t)
+    data = 0.5 * float(np.sum(problem.W_t(t) * d * d))
+    reg = problem.lam * prior.value(w, problem.reg, problem.reg_param, problem.bc)
+    e = w - u
+    return data + reg + 0.5 * float(np.sum(problem.alpha_t(t) * e * e))
+
+
+def prox_gradient(problem, t, w, u):
+    """Gradient of the smooth part of the prox objective at w."""
+    r = problem.W_t(t) * (problem.H(t, w) - problem.y_t(t))
+    g = problem.Ht(t, r)
+    g = g + problem.lam * prior.gradient(w, problem.reg, problem.reg_param, problem.bc)
+    return g + problem.alpha_t(t) * (w - u)
+
+
+def local_solve(problem, t, w0, u, n_inner, tau=None):
+    """n_inner projected-gradient steps on the prox subproblem of tile t."""
+    tau = step_size(problem, t) if tau is None else tau
+    w = w0.copy()
+    for _ in range(n_inner):
+        w = w - tau * prox_gradient(problem, t, w, u)
+        if problem.positivity:
+            w = np.maximum(w, 0.0)
+    return w
+
+
+def initial_tiles(problem, mode="observed"):
+    """x^0 per tile ('zero' or 'observed'); u^0 = x^0.
+
+    'observed': max(y, 0) read at the nearest observed pixel (coordinates
+    clamped into [0, M)), so all tiles start from one common image on X.
+    """
+    L = problem.layout
+    out = []
+    for t in range(problem.n_tiles):
+        shape = L.support_shape(t)
+        if mode == "zero":
+            out.append(np.zeros(shape))
+            continue
+        if mode != "observed":
+            raise ValueError(mode)
+        (y0, y1), (x0, x1) = L.support(t)
+        iy = np.clip(np.arange(y0, y1), 0, L.ay.M - 1)
+        ix = np.clip(np.arange(x0, x1), 0, L.ax.M - 1)
+        out.append(np.maximum(problem.y[np.ix_(iy, ix)], 0.0))
+    return out
+
+
+def consensus_average(problem, v_tiles):
+    """zbar on X: the alpha-weighted average of the tiles covering each pixel
+    (the Lemma of Section III-B).  Returns (zbar, coverage count)."""
+    L = problem.layout
+    r = L.r
+    num = np.zeros(L.X_shape)
+    den = np.zeros(L.X_shape)
+    cnt = np.zeros(L.X_shape, dtype=np.int64)
+    for t in range(problem.n_tiles):
+        (y0, y1), (x0, x1) = L.support(t)
+        a = problem.alpha_t(t)
+        sl = (slice(y0 + r, y1 + r), slice(x0 + r, x1 + r))
+        num[sl] += a * v_tiles[t]
+        den[sl] += a
+        cnt[sl] += 1
+    return num / den, cnt
+
+
+def consensus_step(problem, x_tiles, u_tiles):
+    """One consensus + dual update; returns (new u tiles, zbar)."""
+    v = [2.0 * x - u for x, u in zip(x_tiles, u_tiles)]
+    zbar, _ = consensus_average(problem, v)
+    out = []
+    for t in range(problem.n_tiles):
+        out.append(u_tiles[t] + problem.rho * (problem.layout.restrict(zbar, t) - x_tiles[t]))
+    return out, zbar
+
+
+def residual(u_old, u_new):
+    num = sum(float(np.sum((a - b) ** 2)) for a, b in zip(u_new, u_old))
+    den = sum(float(np.sum(a * a)) for a in u_new)
+    return float(np.sqrt(num / den)) if den > 0 else 0.0
+
+
+def assemble(problem, x_tiles):
+    """x_hat = sum_t omega_t x_t on X (the consensus image at convergence)."""
+    L = problem.layout
+    r = L.r
+    out = np.zeros(L.X_shape)
+    for t in range(problem.n_tiles):
+        (y0, y1), (x0, x1) = L.support(t)
+        out[y0 + r:y1 + r, x0 + r:x1 + r] += L.omega(t) * x_tiles[t]
+    return out
+
+
+@dataclasses.dataclass
+class Result:
+    x: list
+    u: list
+    residuals: list
+    x_hat: np.ndarray
+
+
+def solve(problem, n_outer, n_inner=10, init="observed", x0=None, inner_growth=0,
+          consensus=True, callback=None):
+    """Algorithm 1 with n_inner(k) = n_inner + inner_growth * k Local-Solver steps.
+
+    ``consensus=False`` skips the consensus step (the paper's 'independent'
+    baseline: each tile is deblurred on its own and the tiles are blended
+    with omega at the end).
+    """
+    x = [a.copy() for a in (x0 if x0 is not None else initial_tiles(problem, init))]
+    u = [a.copy() for a in x]
+    taus = [step_size(problem, t) for t in range(problem.n_tiles)]
+    res = []
+    for k in range(n_outer):
+        n_k = n_inner + inner_growth * k
+        x = [local_solve(problem, t, x[t], u[t], n_k, taus[t]) for t in range(problem.n_tiles)]
+        if consensus:
+            u_new, _ = consensus_step(problem, x, u)
+        else:
+            # Independent tiles: each runs the proximal-point method on its own
+            # f_t (u <- x), which converges to argmin f_t.
+            u_new = [a.copy() for a in x]
+        res.append(residual(u, u_new))
+        u = u_new
+        if callback is not None:
+            callback(k, x, u)
+    return Result(x, u, res, assemble(problem, x))

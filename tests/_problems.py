@@ -1,0 +1,29 @@
+"""Small seeded problems shared by the oracle pins and the GPU parity tests."""
+import numpy as np
+
+from oracle.layout import make_layout
+from oracle.solver import Problem
+
+
+def random_psfs(G_y, G_x, P, seed, positive=True):
+    """Asymmetric random PSFs (non-negative, unit sum) so flips and
+    transposes show up."""
+    rng = np.random.default_rng(seed)
+    h = rng.random((G_y, G_x, P, P)) ** 3
+    if not positive:
+        h = rng.standard_normal((G_y, G_x, P, P))
+        return h
+    return h / h.sum(axis=(2, 3), keepdims=True)
+
+
+def tiny_problem(M=12, T=2, p=6, o=2, P=3, G=2, seed=0, model="interp", lam=1e-2,
+                 reg="tv", reg_param=0.05, gamma=0.5, positivity=True, bc="neumann",
+                 W_random=True, M_x=None, T_x=None, G_x=None):
+    L = make_layout(M, T, p, o, P, G, model=model, M_x=M_x, T_x=T_x, G_x=G_x)
+    rng = np.random.default_rng(seed + 100)
+    psfs = random_psfs(L.ay.G, L.ax.G, P, seed)
+    My, Mx = L.ay.M, L.ax.M
+    y = rng.random((My, Mx)) + 0.1
+    W = (0.5 + rng.random((My, Mx))) if W_random else np.ones((My, Mx))
+    return Problem(L, psfs, y, W, lam=lam, reg=reg, reg_param=reg_param, gamma=gamma,
+                   positivity=positivity, bc=bc)
