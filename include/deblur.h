@@ -1,0 +1,217 @@
+/*
+ * deblur.h -- C ABI of the MI355X tile solver for distributed non-blind
+ * deblurring (Mourya, Ferrari, Flamary, Bianchi, Richard: "Distributed
+ * Deblurring of Large Images of Wide Field-Of-View").
+ *
+ * All tiles of the paper's distributed formulation (Section III-A) live on
+ * one GPU as a single batch.  The library owns every device buffer it needs;
+ * after deblur_create() no call allocates memory.  Every call is ordered on
+ * the HIP stream given at creation and is not thread-safe for one context
+ * (several contexts may coexist).
+ *
+ * Pointers: "device" arguments are HIP device pointers that must stay valid
+ * until the context stream has finished the call's work; "host" arguments
+ * are ordinary host memory read or written before the call returns.
+ * All floating-point data are IEEE fp32, row-major, no padding.
+ *
+ * Return values: DEBLUR_OK (0) or a negative DEBLUR_E_* code.  A failing
+ * call leaves a message retrievable with deblur_last_error(ctx); failures of
+ * deblur_create are reported by deblur_last_error(NULL).  No C++ exception
+ * crosses this interface.
+ *
+ * Geometry (Section III-A, Fig. 1).  The observed image y is M_y x M_x.  The
+ * unknown image x lives on X = [-r, M_y + r) x [-r, M_x + r), r = P/2.
+ * Along one axis, block a covers observed pixels [a*pitch, min(a*pitch +
+ * pitch + overlap, M)) for a < T-1 and [(T-1)*pitch, M) for the last block;
+ * its support (the unknowns the tile estimates) is the block dilated by r.
+ * Tile t = a * T_x + b.  Consensus weights omega_t are 1 inside a support
+ * and ramp linearly, (s + 1/2)/L, across each overlap of length
+ * L = overlap + 2r, so they sum to one over the tiles covering a pixel.
+ *
+ * Packed tile layouts used by apply_H / apply_Ht / get_state / set_state:
+ *   "support-packed": tile after tile, each tile's support_h x support_w
+ *                     pixels row-major, starting at desc.x_offset floats;
+ *   "block-packed":   tile after tile, each block_h x block_w observed
+ *                     pixels row-major, starting at desc.y_offset floats.
+ */
+#ifndef DEBLUR_H
+#define DEBLUR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct deblur_ctx deblur_ctx;
+
+enum {
+    DEBLUR_OK = 0,
+    DEBLUR_E_ARG = -1,       /* bad pointer or parameter value            */
+    DEBLUR_E_SHAPE = -2,     /* geometry the library cannot tile          */
+    DEBLUR_E_OOM = -3,       /* device allocation failed (create only)    */
+    DEBLUR_E_HIP = -4,       /* a HIP runtime call failed                 */
+    DEBLUR_E_STATE = -5,     /* call out of order (e.g. no observation)   */
+    DEBLUR_E_NONFINITE = -6  /* a residual or objective was not finite    */
+};
+
+/* Blur model of a tile (Section II-B). */
+enum {
+    DEBLUR_MODEL_INTERP = 0, /* sum_k h_k * (w_k . x) over the PSF nodes whose first-order
+                                interpolation weight w_k touches the tile */
+    DEBLUR_MODEL_LOCAL = 1   /* the tile's own PSF only, H_i = C_i calH_i (needs G = T)   */
+};
+
+/* Regulariser phi(D x) (Section IV-A), D = forward differences. */
+enum {
+    DEBLUR_REG_SMOOTH_TV = 0, /* sum sqrt(|Dx|^2 + eps^2) - eps            */
+    DEBLUR_REG_HUBER = 1      /* per-pixel Huber of |Dx| with threshold delta */
+};
+
+enum {
+    DEBLUR_BC_NEUMANN = 0,    /* difference 0 at the support's last row/column */
+    DEBLUR_BC_CIRCULAR = 1    /* difference wraps within the support           */
+};
+
+enum {
+    DEBLUR_INIT_ZERO = 0,     /* x0 = 0                                          */
+    DEBLUR_INIT_OBSERVED = 1, /* x0 = max(y, 0) at the nearest observed pixel     */
+    DEBLUR_INIT_GIVEN = 2     /* x0 from a support-packed device array             */
+};
+
+typedef struct deblur_params {
+    int32_t M_y, M_x;     /* observed image size                          */
+    int32_t T_y, T_x;     /* tiles per axis                               */
+    int32_t pitch;        /* tile pitch p                                 */
+    int32_t overlap;      /* block overlap o (overlap + 2r <= pitch)      */
+    int32_t G_y, G_x;     /* PSF grid nodes per axis                      */
+    int32_t P;            /* PSF size, odd; r = P / 2                     */
+    int32_t model;        /* DEBLUR_MODEL_*                               */
+    int32_t reg;          /* DEBLUR_REG_*                                 */
+    int32_t bc;           /* DEBLUR_BC_*                                  */
+    int32_t positivity;   /* 1: x >= 0 constraint of Eq. (3), 0: none     */
+    int32_t fft_size;     /* 0: chosen by the library; else 160/320/640   */
+    float lambda;         /* regularisation weight                        */
+    float reg_param;      /* eps (smoothed TV) or delta (Huber), > 0      */
+    float gamma;          /* metric alpha_t = gamma * omega_t, > 0        */
+    float rho;            /* D-R relaxation, in (0, 2)                    */
+} deblur_params;
+
+typedef struct deblur_tile_desc {
+    int32_t support_y0, support_x0; /* observed coordinate of the first support pixel (>= -r) */
+    int32_t support_h, support_w;
+    int32_t block_y0, block_x0;     /* observed coordinate of the first block pixel          */
+    int32_t block_h, block_w;
+    int64_t x_offset;               /* float offset of the tile in support-packed arrays     */
+    int64_t y_offset;               /* float offset of the tile in block-packed arrays       */
+    int32_t n_terms;                /* PSF terms K_t of the tile's operator                  */
+    int32_t frame;                  /* FFT frame size used for the tile                      */
+} deblur_tile_desc;
+
+/* Create a context.  psfs_host: host [G_y][G_x][P][P] fp32, PSF of node
+ * (ky, kx) sampled at offsets q in [-r, r]^2 (index q + r); the operator is
+ * the true convolution (H x)(j) = sum_q h(q) x(j - q).  stream: a
+ * hipStream_t (NULL = default stream).  Validates the geometry (overlap + 2r
+ * <= pitch, every block >= P, supports fit the largest frame 640), allocates
+ * all device memory, computes the PSF spectra.  *out receives the context. */
+int deblur_create(const deblur_params* params, const float* psfs_host, void* stream,
+                  deblur_ctx** out);
+
+void deblur_destroy(deblur_ctx* ctx);
+
+/* Message of the last failing call on ctx (ctx == NULL: last failing create
+ * on this thread).  Valid until the next call on the same context. */
+const char* deblur_last_error(const deblur_ctx* ctx);
+
+/* Copy up to cap tile descriptors to host memory desc_host; writes the total
+ * float counts of support- and block-packed arrays to *support_total and
+ * *block_total (either may be NULL).  Returns the number of tiles. */
+int deblur_tile_layout(const deblur_ctx* ctx, deblur_tile_desc* desc_host, int32_t cap,
+                       int64_t* support_total, int64_t* block_total);
+
+/* Set the observation: y and w are device [M_y][M_x]; w = NULL means W = 1.
+ * W is the inverse-variance weight of Eq. (3) (0 marks unmeasured pixels)
+ * and must be finite and >= 0.  Computes each tile's step size
+ * tau_t = 1 / (max_Bt W * max_Bt (H_t 1) + lambda * L_phi + gamma), with
+ * L_phi = 8/eps (TV) or 8 (Huber). */
+int deblur_set_observation(deblur_ctx* ctx, const float* y, const float* w);
+
+/* Forward operator of every tile (Section II-B):
+ * y_t(j) = sum_k sum_q h_k(q) w_k(j - q) x_t(j - q) for j in block B_t.
+ * x_tiles: device, support-packed; y_tiles: device, block-packed. */
+int deblur_apply_H(deblur_ctx* ctx, const float* x_tiles, float* y_tiles);
+
+/* Adjoint of deblur_apply_H: x_t(i) = sum_k w_k(i) sum_q h_k(q) s_t(i + q).
+ * s_tiles: device, block-packed; x_tiles: device, support-packed. */
+int deblur_apply_Ht(deblur_ctx* ctx, const float* s_tiles, float* x_tiles);
+
+/* Set x^0 and u^0 = x^0 (Algorithm 1's initialisation).  x0_tiles (device,
+ * support-packed) is read only for DEBLUR_INIT_GIVEN.  Needs an observation. */
+int deblur_init(deblur_ctx* ctx, int32_t mode, const float* x0_tiles);
+
+/* n_inner Local-Solver steps on every tile (Algorithm 1, first loop):
+ * projected gradient on f_t(w) + 1/2 ||w - u_t||^2_alpha,
+ *   w <- max(0, w - tau_t (H^T W (H w - y) + lambda grad phi(w) + alpha (w - u))),
+ * warm-started from the current x (Section IV-B). */
+int deblur_solve_tiles(deblur_ctx* ctx, int32_t n_inner);
+
+/* Consensus and dual update (Lemma of Section III-B and Algorithm 1):
+ * zbar = sum_t omega_t (2 x_t - u_t) / sum_t omega_t over the tiles covering
+ * each pixel, u_t <- u_t + rho (zbar - x_t).  *residual_host (may be NULL)
+ * receives ||u_new - u_old|| / ||u_new|| over all tiles. */
+int deblur_consensus(deblur_ctx* ctx, double* residual_host);
+
+/* Algorithm 1: up to n_outer rounds of (n_inner Local-Solver steps +
+ * consensus), each round one captured HIP graph.  Stops after the first
+ * round whose residual is <= tol (tol <= 0: run all rounds without host
+ * synchronisation in between).  residuals_host (may be NULL) receives one
+ * value per round run; *rounds_done the number of rounds. */
+int deblur_run(deblur_ctx* ctx, int32_t n_outer, int32_t n_inner, double tol,
+               double* residuals_host, int32_t* rounds_done);
+
+/* Checkpoint / restore (x, u), device support-packed arrays. */
+int deblur_get_state(deblur_ctx* ctx, float* x_tiles, float* u_tiles);
+int deblur_set_state(deblur_ctx* ctx, const float* x_tiles, const float* u_tiles);
+
+/* Output image x_hat = sum_t omega_t x_t on X: device [M_y + 2r][M_x + 2r]. */
+int deblur_assemble(deblur_ctx* ctx, float* x_global);
+
+/* Objective terms summed over tiles at the current (x, u), host doubles:
+ * out[0] = sum 1/2 ||y_t - H_t x_t||^2_W, out[1] = sum lambda phi(D x_t),
+ * out[2] = sum 1/2 ||x_t - u_t||^2_alpha. */
+int deblur_objective(deblur_ctx* ctx, double* out_host);
+
+/* Per-tile step sizes tau_t (host float[n_tiles]); needs an observation. */
+int deblur_step_sizes(deblur_ctx* ctx, float* tau_host);
+
+/* Image formation without noise (Eq. (2)): y = R sum_k Z_k H_k W_k C_k x for a
+ * device image x_global on X, written to device y_global [M_y][M_x].  Each
+ * observed pixel is taken from the tile whose block owns it. */
+int deblur_blur_global(deblur_ctx* ctx, const float* x_global, float* y_global);
+
+/* Kernel timing: launches each kernel of one Local-Solver step and of the
+ * consensus step reps times between HIP events on the context stream and
+ * writes the mean milliseconds per launch to ms_host[DEBLUR_N_KERNELS] in the
+ * order col_H, row_resid, col_Ht, row_update, consensus.  The state (x, u)
+ * is saved and restored around the measurement. */
+enum { DEBLUR_N_KERNELS = 5 };
+int deblur_time_kernels(deblur_ctx* ctx, int32_t reps, float* ms_host);
+
+/* Diagnostic access to the FFT core, one stage at a time (synchronous on
+ * stream).  n in {160, 320, 640}; batch frames; all data device fp32,
+ * complex values as interleaved (re, im) pairs:
+ *   which = 0: row R2C.  in [batch][n][n] real -> out [batch][n/2][n]
+ *              complex, out[b][f][i] = sum_c in[b][i][c] e^{-2 pi i f c/n}
+ *              for 1 <= f < n/2 and out[b][0][i] = DC + i Nyquist of row i;
+ *   which = 1: forward column FFT.  in, out [batch][n/2][n] complex,
+ *              out[b][f][g] = sum_m in[b][f][m] e^{-2 pi i g m/n};
+ *   which = 2: unnormalised inverse column FFT (e^{+2 pi i g m/n});
+ *   which = 3: row C2R, the inverse of which = 0 times n/2:
+ *              in [batch][n/2][n] complex -> out [batch][n][n] real. */
+int deblur_debug_fft(int32_t n, int32_t batch, int32_t which, const float* in, float* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEBLUR_H */

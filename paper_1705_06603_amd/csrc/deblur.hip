@@ -1,0 +1,990 @@
+// Host side of the MI355X tile solver: context, layout tables, launches,
+// HIP-graph capture of the D-R rounds and the C ABI declared in deblur.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/deblur.h"
+#include "kernels.h"
+
+using dbl::Cover;
+using dbl::PackDesc;
+using dbl::SolveParams;
+using dbl::TileInfo;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr int kFrames[3] = {160, 320, 640};
+constexpr int kResCap = 4096;
+
+// One axis of the tiling and of the PSF grid (Section III-A, Fig. 1).
+struct Axis {
+    int M, T, p, o, r, G;
+
+    void block(int a, int& s, int& e) const {
+        s = a * p;
+        e = (a == T - 1) ? M : std::min(a * p + p + o, M);
+    }
+    void support(int a, int& s, int& e) const {
+        block(a, s, e);
+        s -= r;
+        e += r;
+    }
+    int support_len(int a) const {
+        int s, e;
+        support(a, s, e);
+        return e - s;
+    }
+    // consensus weight of tile a at support offset m
+    double omega(int a, int m) const {
+        int s0, s1;
+        support(a, s0, s1);
+        double w = 1.0;
+        if (a > 0) {
+            int ps, pe;
+            support(a - 1, ps, pe);
+            const int L = pe - s0;
+            if (m < L) w = (m + 0.5) / L;
+        }
+        if (a < T - 1) {
+            int ns, ne;
+            support(a + 1, ns, ne);
+            const int L = s1 - ns;
+            const int s = (s0 + m) - ns;
+            if (s >= 0) w = (L - s - 0.5) / L;
+        }
+        return w;
+    }
+    double centre(int k) const { return (k + 0.5) * ((double)M / G) - 0.5; }
+    // first-order interpolation weight of node k at observed coordinate c
+    double tent(int k, double c) const {
+        const double q = (double)M / G, ck = centre(k);
+        if (k == 0 && c <= ck) return 1.0;
+        if (k == G - 1 && c >= ck) return 1.0;
+        return std::max(0.0, 1.0 - std::fabs(c - ck) / q);
+    }
+    std::vector<int> nodes(int a) const {
+        int s0, s1;
+        support(a, s0, s1);
+        std::vector<int> out;
+        for (int k = 0; k < G; ++k) {
+            bool any = false;
+            for (int c = s0; c < s1 && !any; ++c) any = tent(k, c) > 0.0;
+            if (any) out.push_back(k);
+        }
+        return out;
+    }
+    std::string validate() const {
+        if (M < 1 || T < 1 || G < 1 || p < 1 || o < 0 || r < 0) return "non-positive size";
+        if (T > 1) {
+            if (o + 2 * r > p) return "overlap + 2r exceeds the pitch";
+            if (M - (T - 1) * p <= o) return "last block does not extend past the previous one";
+        } else if (p < M && T == 1) {
+            // a single tile always covers the whole axis
+        }
+        for (int a = 0; a < T; ++a) {
+            int s, e;
+            block(a, s, e);
+            if (e - s < 2 * r + 1) return "a block is smaller than the PSF";
+        }
+        return "";
+    }
+};
+
+}  // namespace
+
+struct deblur_ctx {
+    deblur_params p{};
+    int r = 0, N = 0, nt = 0, nodes = 0, Xy = 0, Xx = 0;
+    Axis ay{}, ax{};
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    std::string err;
+
+    std::vector<TileInfo> tiles_h;
+    std::vector<deblur_tile_desc> desc;
+    std::vector<float> omega_max;
+    int64_t support_total = 0, block_total = 0;
+
+    TileInfo* tiles = nullptr;
+    float *tentY = nullptr, *tentX = nullptr, *omY = nullptr, *omX = nullptr;
+    Cover *covY = nullptr, *covX = nullptr;
+    int *sorg = nullptr, *borg = nullptr, *xorg = nullptr;
+    PackDesc *pd_support = nullptr, *pd_block = nullptr;
+    float2* tw = nullptr;
+    float2* spec = nullptr;
+    float* x[2] = {nullptr, nullptr};
+    int cur = 0;
+    float* u = nullptr;
+    float2* yw = nullptr;
+    float* frame_tmp = nullptr;
+    float* frame_tmp2 = nullptr;
+    float2 *Zk = nullptr, *Yc = nullptr, *Rr = nullptr, *Gk = nullptr;
+    float* obj_part = nullptr;
+    float2* cons_part = nullptr;
+    int cons_nparts = 0;
+    double* res_hist = nullptr;
+    int* res_counter = nullptr;
+    double* res_last = nullptr;
+    double* reg_part = nullptr;
+    int reg_blocks = 8;
+    float* tau = nullptr;
+    float* maxW = nullptr;
+    float* rowsum = nullptr;
+    float* y_glob = nullptr;
+    double* h_pinned = nullptr;
+    bool have_obs = false;
+    bool have_state = false;
+    std::vector<void*> allocs;
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    std::vector<hipGraph_t> graph_defs;
+};
+
+namespace {
+
+int fail(deblur_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+#define HIP_TRY(ctx, call)                                                                         \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail((ctx), DEBLUR_E_HIP, std::string(#call ": ") + hipGetErrorString(e_));     \
+    } while (0)
+
+int check_launch(deblur_ctx* c, const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, DEBLUR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return DEBLUR_OK;
+}
+
+template <class T>
+int dev_alloc(deblur_ctx* c, T** ptr, size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, DEBLUR_E_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    c->allocs.push_back(p);
+    *ptr = static_cast<T*>(p);
+    return DEBLUR_OK;
+}
+
+size_t frame_elems(const deblur_ctx* c) { return (size_t)c->nt * c->N * c->N; }
+size_t half_elems(const deblur_ctx* c) { return (size_t)c->nt * (c->N / 2) * c->N; }
+
+// ---------------------------------------------------------------------------
+// Launch helpers (dispatch on the frame size)
+// ---------------------------------------------------------------------------
+
+template <int N>
+void launch_row_fwd(deblur_ctx* c, hipStream_t s, const float* x, float2* out, int masked) {
+    using C = dbl::Cfg<N>;
+    hipLaunchKernelGGL(dbl::k_row_fwd<N>, dim3(C::RG, c->nt), dim3(C::NT), 0, s, x, c->tiles, c->tentX, c->tw, out,
+                       masked);
+}
+template <int N>
+void launch_row_inv(deblur_ctx* c, hipStream_t s, const float2* in, float* out, int masked) {
+    using C = dbl::Cfg<N>;
+    hipLaunchKernelGGL(dbl::k_row_inv<N>, dim3(C::RG, c->nt), dim3(C::NT), 0, s, in, c->tiles, c->tentX, c->tw, out,
+                       masked);
+}
+template <int N>
+void launch_col_H(deblur_ctx* c, hipStream_t s) {
+    using C = dbl::Cfg<N>;
+    hipLaunchKernelGGL(dbl::k_col_H<N>, dim3(C::CG, c->nt), dim3(C::NT), 0, s, c->Zk, c->tiles, c->tentY, c->spec,
+                       c->tw, c->Yc);
+}
+template <int N>
+void launch_row_resid(deblur_ctx* c, hipStream_t s) {
+    using C = dbl::Cfg<N>;
+    hipLaunchKernelGGL(dbl::k_row_resid<N>, dim3(C::RG, c->nt), dim3(C::NT), 0, s, c->Yc, c->yw, c->tw, c->Rr,
+                       c->obj_part);
+}
+template <int N>
+void launch_col_Ht(deblur_ctx* c, hipStream_t s) {
+    using C = dbl::Cfg<N>;
+    hipLaunchKernelGGL(dbl::k_col_Ht<N>, dim3(C::CG, c->nt), dim3(C::NT), 0, s, c->Rr, c->tiles, c->tentY, c->spec,
+                       c->tw, c->Gk);
+}
+SolveParams solve_params(const deblur_ctx* c) {
+    SolveParams P;
+    P.lambda = c->p.lambda;
+    P.reg_param = c->p.reg_param;
+    P.gamma = c->p.gamma;
+    P.rho = c->p.rho;
+    P.reg = c->p.reg;
+    P.bc = c->p.bc;
+    P.positivity = c->p.positivity;
+    P.r = c->r;
+    return P;
+}
+template <int N>
+void launch_row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn) {
+    using C = dbl::Cfg<N>;
+    hipLaunchKernelGGL(dbl::k_row_update<N>, dim3(C::RG, c->nt), dim3(C::NT), 0, s, c->Gk, xc, c->u, c->tiles,
+                       c->tentX, c->omY, c->omX, c->tau, solve_params(c), c->tw, xn, c->Zk);
+}
+
+template <int N>
+void launch_col_fft_dbg(deblur_ctx* c, hipStream_t s, const float2* in, float2* out, int dir) {
+    using C = dbl::Cfg<N>;
+    hipLaunchKernelGGL(dbl::k_col_fft_dbg<N>, dim3(C::CG, c->nt), dim3(C::NT), 0, s, in, c->tw, out, dir);
+}
+
+#define DISPATCH_N(c, fn, ...)                                            \
+    do {                                                                  \
+        switch ((c)->N) {                                                 \
+            case 160: fn<160>(c, __VA_ARGS__); break;                     \
+            case 320: fn<320>(c, __VA_ARGS__); break;                     \
+            default: fn<640>(c, __VA_ARGS__); break;                      \
+        }                                                                 \
+    } while (0)
+
+void row_fwd(deblur_ctx* c, hipStream_t s, const float* x, float2* out, int masked) {
+    DISPATCH_N(c, launch_row_fwd, s, x, out, masked);
+}
+void row_inv(deblur_ctx* c, hipStream_t s, const float2* in, float* out, int masked) {
+    DISPATCH_N(c, launch_row_inv, s, in, out, masked);
+}
+void col_H(deblur_ctx* c, hipStream_t s) { DISPATCH_N(c, launch_col_H, s); }
+void row_resid(deblur_ctx* c, hipStream_t s) { DISPATCH_N(c, launch_row_resid, s); }
+void col_Ht(deblur_ctx* c, hipStream_t s) { DISPATCH_N(c, launch_col_Ht, s); }
+void row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn) {
+    DISPATCH_N(c, launch_row_update, s, xc, xn);
+}
+
+int row_groups(const deblur_ctx* c) {
+    switch (c->N) {
+        case 160: return dbl::Cfg<160>::RG;
+        case 320: return dbl::Cfg<320>::RG;
+        default: return dbl::Cfg<640>::RG;
+    }
+}
+
+dim3 pix_grid(const deblur_ctx* c) {
+    return dim3((c->Xx + dbl::kPixBlock - 1) / dbl::kPixBlock, c->Xy);
+}
+
+dim3 frame_grid(const deblur_ctx* c) {
+    const int per = (c->N * c->N + 255) / 256;
+    return dim3(std::min(per, 64), c->nt);
+}
+
+// One Local-Solver step on every tile: x[cur] -> x[1 - cur].
+void inner_step(deblur_ctx* c, hipStream_t s, int parity) {
+    col_H(c, s);
+    row_resid(c, s);
+    col_Ht(c, s);
+    row_update(c, s, c->x[parity], c->x[1 - parity]);
+}
+
+void consensus_launch(deblur_ctx* c, hipStream_t s, int parity) {
+    hipLaunchKernelGGL(dbl::k_consensus, pix_grid(c), dim3(dbl::kPixBlock), 0, s, c->x[parity], c->u, c->covY,
+                       c->covX, c->Xy, c->Xx, c->p.T_x, c->N, c->p.rho, c->cons_part);
+    hipLaunchKernelGGL(dbl::k_finalize_residual, dim3(1), dim3(256), 0, s, c->cons_part, c->cons_nparts,
+                       c->res_hist, c->res_counter, c->res_last, kResCap);
+}
+
+// Forward row transforms of the current iterate (start of the next step).
+void refresh_spectra(deblur_ctx* c, hipStream_t s) { row_fwd(c, s, c->x[c->cur], c->Zk, 1); }
+
+// ---------------------------------------------------------------------------
+// Layout tables
+// ---------------------------------------------------------------------------
+
+int build_layout(deblur_ctx* c, const float* psfs_host) {
+    const deblur_params& p = c->p;
+    c->r = p.P / 2;
+    c->ay = Axis{p.M_y, p.T_y, p.pitch, p.overlap, c->r, p.G_y};
+    c->ax = Axis{p.M_x, p.T_x, p.pitch, p.overlap, c->r, p.G_x};
+    std::string e = c->ay.validate();
+    if (e.empty()) e = c->ax.validate();
+    if (!e.empty()) return fail(nullptr, DEBLUR_E_SHAPE, "geometry: " + e);
+    if (p.model == DEBLUR_MODEL_LOCAL && (p.G_y != p.T_y || p.G_x != p.T_x))
+        return fail(nullptr, DEBLUR_E_SHAPE, "local model needs one PSF node per tile");
+    c->nt = p.T_y * p.T_x;
+    c->nodes = p.G_y * p.G_x;
+    c->Xy = p.M_y + 2 * c->r;
+    c->Xx = p.M_x + 2 * c->r;
+    int smax = 0;
+    for (int a = 0; a < p.T_y; ++a) smax = std::max(smax, c->ay.support_len(a));
+    for (int b = 0; b < p.T_x; ++b) smax = std::max(smax, c->ax.support_len(b));
+    if (p.fft_size) {
+        if (p.fft_size != 160 && p.fft_size != 320 && p.fft_size != 640)
+            return fail(nullptr, DEBLUR_E_ARG, "fft_size must be 0, 160, 320 or 640");
+        if (p.fft_size < smax) return fail(nullptr, DEBLUR_E_SHAPE, "fft_size smaller than a tile support");
+        c->N = p.fft_size;
+    } else {
+        c->N = 0;
+        for (int f : kFrames)
+            if (f >= smax) {
+                c->N = f;
+                break;
+            }
+        if (!c->N) return fail(nullptr, DEBLUR_E_SHAPE, "tile support larger than the largest frame (640)");
+    }
+    const int N = c->N;
+    // PSF checks
+    for (int i = 0; i < c->nodes * p.P * p.P; ++i)
+        if (!std::isfinite(psfs_host[i])) return fail(nullptr, DEBLUR_E_ARG, "non-finite PSF value");
+    (void)psfs_host;
+
+    std::vector<std::vector<int>> ny(p.T_y), nx(p.T_x);
+    for (int a = 0; a < p.T_y; ++a)
+        ny[a] = (p.model == DEBLUR_MODEL_LOCAL) ? std::vector<int>{a} : c->ay.nodes(a);
+    for (int b = 0; b < p.T_x; ++b)
+        nx[b] = (p.model == DEBLUR_MODEL_LOCAL) ? std::vector<int>{b} : c->ax.nodes(b);
+    for (auto& v : ny)
+        if (v.size() > (size_t)dbl::kMaxK) return fail(nullptr, DEBLUR_E_SHAPE, "more than 3 PSF nodes per tile axis");
+    for (auto& v : nx)
+        if (v.size() > (size_t)dbl::kMaxK) return fail(nullptr, DEBLUR_E_SHAPE, "more than 3 PSF nodes per tile axis");
+
+    c->tiles_h.resize(c->nt);
+    c->desc.resize(c->nt);
+    c->omega_max.resize(c->nt);
+    int64_t xo = 0, yo = 0;
+    for (int a = 0; a < p.T_y; ++a)
+        for (int b = 0; b < p.T_x; ++b) {
+            const int t = a * p.T_x + b;
+            TileInfo& ti = c->tiles_h[t];
+            int bs0, be0, bs1, be1, ss0, se0, ss1, se1;
+            c->ay.block(a, bs0, be0);
+            c->ax.block(b, bs1, be1);
+            c->ay.support(a, ss0, se0);
+            c->ax.support(b, ss1, se1);
+            ti.ty = a;
+            ti.tx = b;
+            ti.sy = se0 - ss0;
+            ti.sx = se1 - ss1;
+            ti.by = be0 - bs0;
+            ti.bx = be1 - bs1;
+            ti.nky = (int)ny[a].size();
+            ti.nkx = (int)nx[b].size();
+            for (int k = 0; k < dbl::kMaxK * dbl::kMaxK; ++k) ti.spec[k] = 0;
+            for (int ky = 0; ky < ti.nky; ++ky)
+                for (int kx = 0; kx < ti.nkx; ++kx) ti.spec[ky * dbl::kMaxK + kx] = ny[a][ky] * p.G_x + nx[b][kx];
+            deblur_tile_desc& d = c->desc[t];
+            d.support_y0 = ss0;
+            d.support_x0 = ss1;
+            d.support_h = ti.sy;
+            d.support_w = ti.sx;
+            d.block_y0 = bs0;
+            d.block_x0 = bs1;
+            d.block_h = ti.by;
+            d.block_w = ti.bx;
+            d.x_offset = xo;
+            d.y_offset = yo;
+            d.n_terms = ti.nky * ti.nkx;
+            d.frame = N;
+            xo += (int64_t)ti.sy * ti.sx;
+            yo += (int64_t)ti.by * ti.bx;
+            double om = 0.0;
+            for (int m = 0; m < ti.sy; ++m) om = std::max(om, c->ay.omega(a, m));
+            double omx = 0.0;
+            for (int m = 0; m < ti.sx; ++m) omx = std::max(omx, c->ax.omega(b, m));
+            c->omega_max[t] = (float)(om * omx);
+        }
+    c->support_total = xo;
+    c->block_total = yo;
+    return DEBLUR_OK;
+}
+
+int upload_tables(deblur_ctx* c, const float* psfs_host) {
+    const deblur_params& p = c->p;
+    const int N = c->N, r = c->r;
+    // tents and omegas per tile row / column
+    std::vector<float> tY((size_t)p.T_y * dbl::kMaxK * N, 0.f), tX((size_t)p.T_x * dbl::kMaxK * N, 0.f);
+    std::vector<float> oY((size_t)p.T_y * N, 0.f), oX((size_t)p.T_x * N, 0.f);
+    auto fill_axis = [&](const Axis& A, int T, std::vector<float>& tent, std::vector<float>& om) {
+        for (int a = 0; a < T; ++a) {
+            int s0, s1;
+            A.support(a, s0, s1);
+            std::vector<int> nodes = (p.model == DEBLUR_MODEL_LOCAL) ? std::vector<int>{a} : A.nodes(a);
+            for (size_t k = 0; k < nodes.size(); ++k)
+                for (int m = 0; m < s1 - s0; ++m)
+                    tent[((size_t)a * dbl::kMaxK + k) * N + m] =
+                        (p.model == DEBLUR_MODEL_LOCAL) ? 1.0f : (float)A.tent(nodes[k], s0 + m);
+            for (int m = 0; m < s1 - s0; ++m) om[(size_t)a * N + m] = (float)A.omega(a, m);
+        }
+    };
+    fill_axis(c->ay, p.T_y, tY, oY);
+    fill_axis(c->ax, p.T_x, tX, oX);
+    // coverage of X rows / columns
+    auto cover_axis = [&](const Axis& A, int T, int Xn) {
+        std::vector<Cover> cv(Xn);
+        for (int I = 0; I < Xn; ++I) {
+            const int coord = I - r;
+            Cover cc{-1, 0, -1, 0, 0.f, 0.f, 0, 0};
+            int found = 0;
+            for (int a = 0; a < T; ++a) {
+                int s0, s1;
+                A.support(a, s0, s1);
+                if (coord >= s0 && coord < s1) {
+                    const int m = coord - s0;
+                    const float w = (float)A.omega(a, m);
+                    if (found == 0) {
+                        cc.a0 = a;
+                        cc.m0 = m;
+                        cc.w0 = w;
+                    } else {
+                        cc.a1 = a;
+                        cc.m1 = m;
+                        cc.w1 = w;
+                    }
+                    ++found;
+                }
+            }
+            cv[I] = cc;
+        }
+        return cv;
+    };
+    std::vector<Cover> cY = cover_axis(c->ay, p.T_y, c->Xy), cX = cover_axis(c->ax, p.T_x, c->Xx);
+    for (const Cover& cc : cY)
+        if (cc.a0 < 0) return fail(c, DEBLUR_E_SHAPE, "an X row is covered by no tile");
+    for (const Cover& cc : cX)
+        if (cc.a0 < 0) return fail(c, DEBLUR_E_SHAPE, "an X column is covered by no tile");
+
+    std::vector<int> so(2 * c->nt), bo(2 * c->nt), xo(2 * c->nt);
+    std::vector<PackDesc> pds(c->nt), pdb(c->nt);
+    for (int t = 0; t < c->nt; ++t) {
+        const deblur_tile_desc& d = c->desc[t];
+        so[2 * t] = d.support_y0;
+        so[2 * t + 1] = d.support_x0;
+        bo[2 * t] = d.block_y0;
+        bo[2 * t + 1] = d.block_x0;
+        xo[2 * t] = d.support_y0 + r;
+        xo[2 * t + 1] = d.support_x0 + r;
+        pds[t] = PackDesc{0, 0, d.support_h, d.support_w, (long long)d.x_offset};
+        pdb[t] = PackDesc{r, r, d.block_h, d.block_w, (long long)d.y_offset};
+    }
+    std::vector<float2> tw(N);
+    std::vector<double2> twd(N);
+    for (int e = 0; e < N; ++e) {
+        const double a = -2.0 * M_PI * (double)e / N;
+        tw[e] = make_float2((float)std::cos(a), (float)std::sin(a));
+        twd[e] = make_double2(std::cos(a), std::sin(a));
+    }
+
+    int rc;
+    if ((rc = dev_alloc(c, &c->tiles, c->nt))) return rc;
+    if ((rc = dev_alloc(c, &c->tentY, tY.size()))) return rc;
+    if ((rc = dev_alloc(c, &c->tentX, tX.size()))) return rc;
+    if ((rc = dev_alloc(c, &c->omY, oY.size()))) return rc;
+    if ((rc = dev_alloc(c, &c->omX, oX.size()))) return rc;
+    if ((rc = dev_alloc(c, &c->covY, cY.size()))) return rc;
+    if ((rc = dev_alloc(c, &c->covX, cX.size()))) return rc;
+    if ((rc = dev_alloc(c, &c->sorg, so.size()))) return rc;
+    if ((rc = dev_alloc(c, &c->borg, bo.size()))) return rc;
+    if ((rc = dev_alloc(c, &c->xorg, xo.size()))) return rc;
+    if ((rc = dev_alloc(c, &c->pd_support, pds.size()))) return rc;
+    if ((rc = dev_alloc(c, &c->pd_block, pdb.size()))) return rc;
+    if ((rc = dev_alloc(c, &c->tw, tw.size()))) return rc;
+    HIP_TRY(c, hipMemcpy(c->tiles, c->tiles_h.data(), c->nt * sizeof(TileInfo), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->tentY, tY.data(), tY.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->tentX, tX.data(), tX.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->omY, oY.data(), oY.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->omX, oX.data(), oX.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->covY, cY.data(), cY.size() * sizeof(Cover), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->covX, cX.data(), cX.size() * sizeof(Cover), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->sorg, so.data(), so.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->borg, bo.data(), bo.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->xorg, xo.data(), xo.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->pd_support, pds.data(), pds.size() * sizeof(PackDesc), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->pd_block, pdb.data(), pdb.size() * sizeof(PackDesc), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
+
+    // PSF spectra
+    float* psf_d = nullptr;
+    double2* twd_d = nullptr;
+    const size_t npsf = (size_t)c->nodes * p.P * p.P;
+    HIP_TRY(c, hipMalloc(&psf_d, npsf * sizeof(float)));
+    HIP_TRY(c, hipMalloc(&twd_d, N * sizeof(double2)));
+    if ((rc = dev_alloc(c, &c->spec, (size_t)c->nodes * (N / 2 + 1) * N))) return rc;
+    HIP_TRY(c, hipMemcpy(psf_d, psfs_host, npsf * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(twd_d, twd.data(), N * sizeof(double2), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(dbl::k_psf_spectra, dim3(std::min(((N / 2 + 1) * N + 255) / 256, 1024), c->nodes),
+                       dim3(256), N * sizeof(double2), c->stream, psf_d, p.P, N, twd_d, c->spec);
+    if ((rc = check_launch(c, "k_psf_spectra"))) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipFree(psf_d));
+    HIP_TRY(c, hipFree(twd_d));
+    return DEBLUR_OK;
+}
+
+int alloc_state(deblur_ctx* c) {
+    int rc;
+    const size_t fe = frame_elems(c), he = half_elems(c);
+    if ((rc = dev_alloc(c, &c->x[0], fe))) return rc;
+    if ((rc = dev_alloc(c, &c->x[1], fe))) return rc;
+    if ((rc = dev_alloc(c, &c->u, fe))) return rc;
+    if ((rc = dev_alloc(c, &c->frame_tmp, fe))) return rc;
+    if ((rc = dev_alloc(c, &c->frame_tmp2, fe))) return rc;
+    if ((rc = dev_alloc(c, &c->yw, fe))) return rc;
+    if ((rc = dev_alloc(c, &c->Zk, he * dbl::kMaxK))) return rc;
+    if ((rc = dev_alloc(c, &c->Gk, he * dbl::kMaxK))) return rc;
+    if ((rc = dev_alloc(c, &c->Yc, he))) return rc;
+    if ((rc = dev_alloc(c, &c->Rr, he))) return rc;
+    if ((rc = dev_alloc(c, &c->obj_part, (size_t)c->nt * row_groups(c)))) return rc;
+    const dim3 pg = pix_grid(c);
+    c->cons_nparts = (int)(pg.x * pg.y);
+    if ((rc = dev_alloc(c, &c->cons_part, c->cons_nparts))) return rc;
+    if ((rc = dev_alloc(c, &c->res_hist, kResCap))) return rc;
+    if ((rc = dev_alloc(c, &c->res_counter, 1))) return rc;
+    if ((rc = dev_alloc(c, &c->res_last, 1))) return rc;
+    if ((rc = dev_alloc(c, &c->reg_part, (size_t)2 * c->nt * c->reg_blocks))) return rc;
+    if ((rc = dev_alloc(c, &c->tau, c->nt))) return rc;
+    if ((rc = dev_alloc(c, &c->maxW, c->nt))) return rc;
+    if ((rc = dev_alloc(c, &c->rowsum, c->nt))) return rc;
+    if ((rc = dev_alloc(c, &c->y_glob, (size_t)c->p.M_y * c->p.M_x))) return rc;
+    HIP_TRY(c, hipHostMalloc((void**)&c->h_pinned, 64 * sizeof(double), hipHostMallocDefault));
+    // zero everything that is read before being written
+    for (float* f : {c->x[0], c->x[1], c->u, c->frame_tmp, c->frame_tmp2})
+        HIP_TRY(c, hipMemsetAsync(f, 0, fe * sizeof(float), c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->yw, 0, fe * sizeof(float2), c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->Zk, 0, he * dbl::kMaxK * sizeof(float2), c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->Gk, 0, he * dbl::kMaxK * sizeof(float2), c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->Yc, 0, he * sizeof(float2), c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->Rr, 0, he * sizeof(float2), c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return DEBLUR_OK;
+}
+
+// H applied to the frames in src (support frames) -> Hx frames in dst.
+void apply_H_frames(deblur_ctx* c, hipStream_t s, const float* src, float* dst) {
+    row_fwd(c, s, src, c->Zk, 1);
+    col_H(c, s);
+    row_inv(c, s, c->Yc, dst, 0);
+}
+
+// Row sums max_Bt (H_t 1) per tile (for the step sizes).
+int compute_rowsums(deblur_ctx* c) {
+    hipLaunchKernelGGL(dbl::k_fill, dim3(1024), dim3(256), 0, c->stream, c->frame_tmp2, 1.0f, frame_elems(c));
+    // ones on the supports only
+    std::vector<float> ones((size_t)c->support_total, 1.0f);
+    float* ones_d = nullptr;
+    HIP_TRY(c, hipMalloc(&ones_d, std::max<size_t>(ones.size(), 1) * sizeof(float)));
+    HIP_TRY(c, hipMemcpy(ones_d, ones.data(), ones.size() * sizeof(float), hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(dbl::k_pack, frame_grid(c), dim3(256), 0, c->stream, ones_d, c->pd_support, c->N,
+                       c->frame_tmp2);
+    apply_H_frames(c, c->stream, c->frame_tmp2, c->frame_tmp);
+    hipLaunchKernelGGL(dbl::k_block_max, dim3(c->nt), dim3(256), 0, c->stream, c->frame_tmp, 1, 0, c->tiles, c->N,
+                       c->r, c->rowsum);
+    int rc = check_launch(c, "row sums");
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipFree(ones_d));
+    return DEBLUR_OK;
+}
+
+int ensure_graph(deblur_ctx* c, int n_inner, int parity, hipGraphExec_t* out) {
+    auto key = std::make_pair(n_inner, parity);
+    auto it = c->graphs.find(key);
+    if (it != c->graphs.end()) {
+        *out = it->second;
+        return DEBLUR_OK;
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    int par = parity;
+    for (int i = 0; i < n_inner; ++i) {
+        inner_step(c, c->cap_stream, par);
+        par = 1 - par;
+    }
+    consensus_launch(c, c->cap_stream, par);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
+    if (e1 != hipSuccess || e2 != hipSuccess)
+        return fail(c, DEBLUR_E_HIP, std::string("graph capture: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+    hipGraphExec_t ex = nullptr;
+    HIP_TRY(c, hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+    c->graph_defs.push_back(g);
+    c->graphs[key] = ex;
+    *out = ex;
+    return DEBLUR_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+const char* deblur_last_error(const deblur_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+void deblur_destroy(deblur_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipGraph_t g : c->graph_defs) (void)hipGraphDestroy(g);
+    for (void* p : c->allocs) (void)hipFree(p);
+    if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+}
+
+int deblur_create(const deblur_params* params, const float* psfs_host, void* stream, deblur_ctx** out) {
+    if (!params || !psfs_host || !out) return fail(nullptr, DEBLUR_E_ARG, "null argument");
+    *out = nullptr;
+    const deblur_params& p = *params;
+    if (p.P < 1 || p.P % 2 == 0) return fail(nullptr, DEBLUR_E_ARG, "P must be odd and positive");
+    if (p.model != DEBLUR_MODEL_INTERP && p.model != DEBLUR_MODEL_LOCAL) return fail(nullptr, DEBLUR_E_ARG, "model");
+    if (p.reg != DEBLUR_REG_SMOOTH_TV && p.reg != DEBLUR_REG_HUBER) return fail(nullptr, DEBLUR_E_ARG, "reg");
+    if (p.bc != DEBLUR_BC_NEUMANN && p.bc != DEBLUR_BC_CIRCULAR) return fail(nullptr, DEBLUR_E_ARG, "bc");
+    if (!(p.reg_param > 0.f) || !(p.gamma > 0.f) || !(p.lambda >= 0.f) || !(p.rho > 0.f && p.rho < 2.f))
+        return fail(nullptr, DEBLUR_E_ARG, "need reg_param > 0, gamma > 0, lambda >= 0, 0 < rho < 2");
+    deblur_ctx* c = new deblur_ctx();
+    c->p = p;
+    c->stream = static_cast<hipStream_t>(stream);
+    int rc = build_layout(c, psfs_host);
+    if (rc) {
+        delete c;
+        return rc;
+    }
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail(nullptr, DEBLUR_E_HIP, "hipStreamCreate failed");
+    }
+    rc = upload_tables(c, psfs_host);
+    if (!rc) rc = alloc_state(c);
+    if (!rc) rc = compute_rowsums(c);
+    if (rc) {
+        g_create_error = c->err;
+        deblur_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return DEBLUR_OK;
+}
+
+int deblur_tile_layout(const deblur_ctx* c, deblur_tile_desc* desc, int32_t cap, int64_t* support_total,
+                       int64_t* block_total) {
+    if (!c) return DEBLUR_E_ARG;
+    if (desc)
+        for (int t = 0; t < std::min<int>(cap, c->nt); ++t) desc[t] = c->desc[t];
+    if (support_total) *support_total = c->support_total;
+    if (block_total) *block_total = c->block_total;
+    return c->nt;
+}
+
+int deblur_set_observation(deblur_ctx* c, const float* y, const float* w) {
+    if (!c || !y) return fail(c, DEBLUR_E_ARG, "null argument");
+    hipLaunchKernelGGL(dbl::k_copy, dim3(1024), dim3(256), 0, c->stream, y, c->y_glob,
+                       (size_t)c->p.M_y * c->p.M_x);
+    hipLaunchKernelGGL(dbl::k_set_obs, frame_grid(c), dim3(256), 0, c->stream, y, w, c->tiles, c->borg, c->p.M_x,
+                       c->N, c->r, c->yw);
+    hipLaunchKernelGGL(dbl::k_block_max, dim3(c->nt), dim3(256), 0, c->stream, reinterpret_cast<float*>(c->yw), 2, 1,
+                       c->tiles, c->N, c->r, c->maxW);
+    int rc = check_launch(c, "set_observation");
+    if (rc) return rc;
+    std::vector<float> mw(c->nt), rs(c->nt), tau(c->nt);
+    HIP_TRY(c, hipMemcpyAsync(mw.data(), c->maxW, c->nt * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(rs.data(), c->rowsum, c->nt * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const double Lphi = (c->p.reg == DEBLUR_REG_SMOOTH_TV) ? 8.0 / c->p.reg_param : 8.0;
+    for (int t = 0; t < c->nt; ++t) {
+        if (!std::isfinite(mw[t]) || mw[t] < 0.f) return fail(c, DEBLUR_E_ARG, "W must be finite and >= 0");
+        const double L = (double)mw[t] * rs[t] + (double)c->p.lambda * Lphi + (double)c->p.gamma * c->omega_max[t];
+        tau[t] = (float)(1.0 / L);
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->tau, tau.data(), c->nt * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->have_obs = true;
+    return DEBLUR_OK;
+}
+
+int deblur_apply_H(deblur_ctx* c, const float* x_tiles, float* y_tiles) {
+    if (!c || !x_tiles || !y_tiles) return fail(c, DEBLUR_E_ARG, "null argument");
+    hipLaunchKernelGGL(dbl::k_pack, frame_grid(c), dim3(256), 0, c->stream, x_tiles, c->pd_support, c->N,
+                       c->frame_tmp2);
+    apply_H_frames(c, c->stream, c->frame_tmp2, c->frame_tmp);
+    hipLaunchKernelGGL(dbl::k_unpack, frame_grid(c), dim3(256), 0, c->stream, c->frame_tmp, c->pd_block, c->N,
+                       y_tiles);
+    int rc = check_launch(c, "apply_H");
+    if (rc) return rc;
+    if (c->have_state) refresh_spectra(c, c->stream);
+    return check_launch(c, "apply_H");
+}
+
+int deblur_apply_Ht(deblur_ctx* c, const float* s_tiles, float* x_tiles) {
+    if (!c || !s_tiles || !x_tiles) return fail(c, DEBLUR_E_ARG, "null argument");
+    hipLaunchKernelGGL(dbl::k_pack, frame_grid(c), dim3(256), 0, c->stream, s_tiles, c->pd_block, c->N,
+                       c->frame_tmp2);
+    row_fwd(c, c->stream, c->frame_tmp2, c->Rr, 0);
+    col_Ht(c, c->stream);
+    row_inv(c, c->stream, c->Gk, c->frame_tmp, 1);
+    hipLaunchKernelGGL(dbl::k_unpack, frame_grid(c), dim3(256), 0, c->stream, c->frame_tmp, c->pd_support, c->N,
+                       x_tiles);
+    return check_launch(c, "apply_Ht");
+}
+
+int deblur_init(deblur_ctx* c, int32_t mode, const float* x0) {
+    if (!c) return DEBLUR_E_ARG;
+    if (!c->have_obs) return fail(c, DEBLUR_E_STATE, "deblur_set_observation must come first");
+    c->cur = 0;
+    if (mode == DEBLUR_INIT_ZERO) {
+        hipLaunchKernelGGL(dbl::k_fill, dim3(1024), dim3(256), 0, c->stream, c->x[0], 0.0f, frame_elems(c));
+        hipLaunchKernelGGL(dbl::k_fill, dim3(1024), dim3(256), 0, c->stream, c->u, 0.0f, frame_elems(c));
+    } else if (mode == DEBLUR_INIT_OBSERVED) {
+        hipLaunchKernelGGL(dbl::k_init_observed, frame_grid(c), dim3(256), 0, c->stream, c->y_glob, c->tiles,
+                           c->sorg, c->p.M_y, c->p.M_x, c->N, c->x[0], c->u);
+    } else if (mode == DEBLUR_INIT_GIVEN) {
+        if (!x0) return fail(c, DEBLUR_E_ARG, "x0 required for DEBLUR_INIT_GIVEN");
+        hipLaunchKernelGGL(dbl::k_pack, frame_grid(c), dim3(256), 0, c->stream, x0, c->pd_support, c->N, c->x[0]);
+        hipLaunchKernelGGL(dbl::k_copy, dim3(1024), dim3(256), 0, c->stream, c->x[0], c->u, frame_elems(c));
+    } else {
+        return fail(c, DEBLUR_E_ARG, "unknown init mode");
+    }
+    refresh_spectra(c, c->stream);
+    c->have_state = true;
+    return check_launch(c, "init");
+}
+
+int deblur_solve_tiles(deblur_ctx* c, int32_t n_inner) {
+    if (!c || n_inner < 0) return fail(c, DEBLUR_E_ARG, "bad argument");
+    if (!c->have_state) return fail(c, DEBLUR_E_STATE, "deblur_init must come first");
+    for (int i = 0; i < n_inner; ++i) {
+        inner_step(c, c->stream, c->cur);
+        c->cur = 1 - c->cur;
+    }
+    return check_launch(c, "solve_tiles");
+}
+
+int deblur_consensus(deblur_ctx* c, double* residual) {
+    if (!c) return DEBLUR_E_ARG;
+    if (!c->have_state) return fail(c, DEBLUR_E_STATE, "deblur_init must come first");
+    hipLaunchKernelGGL(dbl::k_set_int, dim3(1), dim3(1), 0, c->stream, c->res_counter, 0);
+    consensus_launch(c, c->stream, c->cur);
+    int rc = check_launch(c, "consensus");
+    if (rc) return rc;
+    HIP_TRY(c, hipMemcpyAsync(c->h_pinned, c->res_last, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (residual) *residual = c->h_pinned[0];
+    if (!std::isfinite(c->h_pinned[0])) return fail(c, DEBLUR_E_NONFINITE, "non-finite consensus residual");
+    return DEBLUR_OK;
+}
+
+int deblur_run(deblur_ctx* c, int32_t n_outer, int32_t n_inner, double tol, double* residuals, int32_t* done) {
+    if (!c || n_outer < 0 || n_inner < 0) return fail(c, DEBLUR_E_ARG, "bad argument");
+    if (n_outer > kResCap) return fail(c, DEBLUR_E_ARG, "n_outer exceeds 4096");
+    if (!c->have_state) return fail(c, DEBLUR_E_STATE, "deblur_init must come first");
+    hipGraphExec_t g[2] = {nullptr, nullptr};
+    int rc = ensure_graph(c, n_inner, c->cur, &g[c->cur]);
+    if (!rc && (n_inner & 1)) rc = ensure_graph(c, n_inner, 1 - c->cur, &g[1 - c->cur]);
+    if (rc) return rc;
+    hipLaunchKernelGGL(dbl::k_set_int, dim3(1), dim3(1), 0, c->stream, c->res_counter, 0);
+    int k = 0;
+    bool nonfinite = false;
+    for (; k < n_outer;) {
+        HIP_TRY(c, hipGraphLaunch(g[c->cur], c->stream));
+        if (n_inner & 1) c->cur = 1 - c->cur;
+        ++k;
+        if (tol > 0.0) {
+            HIP_TRY(c, hipMemcpyAsync(c->h_pinned, c->res_last, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            if (!std::isfinite(c->h_pinned[0])) {
+                nonfinite = true;
+                break;
+            }
+            if (c->h_pinned[0] <= tol) break;
+        }
+    }
+    if (residuals && k > 0)
+        HIP_TRY(c, hipMemcpyAsync(residuals, c->res_hist, k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (done) *done = k;
+    if (nonfinite) return fail(c, DEBLUR_E_NONFINITE, "non-finite consensus residual");
+    if (residuals)
+        for (int i = 0; i < k; ++i)
+            if (!std::isfinite(residuals[i])) return fail(c, DEBLUR_E_NONFINITE, "non-finite consensus residual");
+    return DEBLUR_OK;
+}
+
+int deblur_get_state(deblur_ctx* c, float* x_tiles, float* u_tiles) {
+    if (!c) return DEBLUR_E_ARG;
+    if (!c->have_state) return fail(c, DEBLUR_E_STATE, "no state yet");
+    if (x_tiles)
+        hipLaunchKernelGGL(dbl::k_unpack, frame_grid(c), dim3(256), 0, c->stream, c->x[c->cur], c->pd_support, c->N,
+                           x_tiles);
+    if (u_tiles)
+        hipLaunchKernelGGL(dbl::k_unpack, frame_grid(c), dim3(256), 0, c->stream, c->u, c->pd_support, c->N,
+                           u_tiles);
+    return check_launch(c, "get_state");
+}
+
+int deblur_set_state(deblur_ctx* c, const float* x_tiles, const float* u_tiles) {
+    if (!c || !x_tiles || !u_tiles) return fail(c, DEBLUR_E_ARG, "null argument");
+    if (!c->have_obs) return fail(c, DEBLUR_E_STATE, "deblur_set_observation must come first");
+    c->cur = 0;
+    hipLaunchKernelGGL(dbl::k_pack, frame_grid(c), dim3(256), 0, c->stream, x_tiles, c->pd_support, c->N, c->x[0]);
+    hipLaunchKernelGGL(dbl::k_pack, frame_grid(c), dim3(256), 0, c->stream, u_tiles, c->pd_support, c->N, c->u);
+    refresh_spectra(c, c->stream);
+    c->have_state = true;
+    return check_launch(c, "set_state");
+}
+
+int deblur_assemble(deblur_ctx* c, float* xg) {
+    if (!c || !xg) return fail(c, DEBLUR_E_ARG, "null argument");
+    if (!c->have_state) return fail(c, DEBLUR_E_STATE, "no state yet");
+    hipLaunchKernelGGL(dbl::k_assemble, pix_grid(c), dim3(dbl::kPixBlock), 0, c->stream, c->x[c->cur], c->covY,
+                       c->covX, c->Xx, c->p.T_x, c->N, xg);
+    return check_launch(c, "assemble");
+}
+
+int deblur_objective(deblur_ctx* c, double* out) {
+    if (!c || !out) return fail(c, DEBLUR_E_ARG, "null argument");
+    if (!c->have_state) return fail(c, DEBLUR_E_STATE, "no state yet");
+    // data term through the same kernels as the solver (Zk holds the current x)
+    col_H(c, c->stream);
+    row_resid(c, c->stream);
+    hipLaunchKernelGGL(dbl::k_reg_terms, dim3(c->reg_blocks, c->nt), dim3(256), 0, c->stream, c->x[c->cur], c->u,
+                       c->tiles, c->omY, c->omX, c->N, solve_params(c), c->reg_part);
+    int rc = check_launch(c, "objective");
+    if (rc) return rc;
+    const int ng = c->nt * row_groups(c);
+    std::vector<float> op(ng);
+    std::vector<double> rp((size_t)2 * c->nt * c->reg_blocks);
+    HIP_TRY(c, hipMemcpyAsync(op.data(), c->obj_part, ng * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(rp.data(), c->reg_part, rp.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double d = 0.0, a = 0.0, b = 0.0;
+    for (float v : op) d += v;
+    for (size_t i = 0; i < rp.size(); i += 2) {
+        a += rp[i];
+        b += rp[i + 1];
+    }
+    out[0] = d;
+    out[1] = (double)c->p.lambda * a;
+    out[2] = b;
+    if (!std::isfinite(d) || !std::isfinite(a) || !std::isfinite(b))
+        return fail(c, DEBLUR_E_NONFINITE, "non-finite objective");
+    return DEBLUR_OK;
+}
+
+int deblur_step_sizes(deblur_ctx* c, float* tau_host) {
+    if (!c || !tau_host) return fail(c, DEBLUR_E_ARG, "null argument");
+    if (!c->have_obs) return fail(c, DEBLUR_E_STATE, "deblur_set_observation must come first");
+    HIP_TRY(c, hipMemcpyAsync(tau_host, c->tau, c->nt * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return DEBLUR_OK;
+}
+
+int deblur_blur_global(deblur_ctx* c, const float* xg, float* yg) {
+    if (!c || !xg || !yg) return fail(c, DEBLUR_E_ARG, "null argument");
+    hipLaunchKernelGGL(dbl::k_scatter_X, frame_grid(c), dim3(256), 0, c->stream, xg, c->tiles, c->xorg, c->Xx, c->N,
+                       c->frame_tmp2);
+    apply_H_frames(c, c->stream, c->frame_tmp2, c->frame_tmp);
+    hipLaunchKernelGGL(dbl::k_gather_owner, dim3((c->p.M_x + 255) / 256, c->p.M_y), dim3(256), 0, c->stream,
+                       c->frame_tmp, c->p.M_y, c->p.M_x, c->p.pitch, c->p.T_y, c->p.T_x, c->N, c->r, yg);
+    int rc = check_launch(c, "blur_global");
+    if (rc) return rc;
+    if (c->have_state) refresh_spectra(c, c->stream);
+    return check_launch(c, "blur_global");
+}
+
+int deblur_time_kernels(deblur_ctx* c, int32_t reps, float* ms) {
+    if (!c || !ms || reps < 1) return fail(c, DEBLUR_E_ARG, "bad argument");
+    if (!c->have_state) return fail(c, DEBLUR_E_STATE, "deblur_init must come first");
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    const int cur = c->cur;
+    // u is modified by the consensus step: keep a copy
+    hipLaunchKernelGGL(dbl::k_copy, dim3(1024), dim3(256), 0, c->stream, c->u, c->frame_tmp, frame_elems(c));
+    for (int which = 0; which < DEBLUR_N_KERNELS; ++which) {
+        auto launch = [&]() {
+            switch (which) {
+                case 0: col_H(c, c->stream); break;
+                case 1: row_resid(c, c->stream); break;
+                case 2: col_Ht(c, c->stream); break;
+                case 3: row_update(c, c->stream, c->x[cur], c->x[1 - cur]); break;
+                default:
+                    hipLaunchKernelGGL(dbl::k_consensus, pix_grid(c), dim3(dbl::kPixBlock), 0, c->stream, c->x[cur],
+                                       c->u, c->covY, c->covX, c->Xy, c->Xx, c->p.T_x, c->N, c->p.rho, c->cons_part);
+                    break;
+            }
+        };
+        launch();   // warm-up
+        HIP_TRY(c, hipEventRecord(e0, c->stream));
+        for (int i = 0; i < reps; ++i) launch();
+        HIP_TRY(c, hipEventRecord(e1, c->stream));
+        HIP_TRY(c, hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&t, e0, e1));
+        ms[which] = t / reps;
+    }
+    hipLaunchKernelGGL(dbl::k_copy, dim3(1024), dim3(256), 0, c->stream, c->frame_tmp, c->u, frame_elems(c));
+    refresh_spectra(c, c->stream);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return check_launch(c, "time_kernels");
+}
+
+int deblur_debug_fft(int32_t n, int32_t batch, int32_t which, const float* in, float* out, void* stream) {
+    if (n != 160 && n != 320 && n != 640) return fail(nullptr, DEBLUR_E_ARG, "n must be 160, 320 or 640");
+    if (batch < 1 || !in || !out || which < 0 || which > 3) return fail(nullptr, DEBLUR_E_ARG, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // A throw-away context with the tables the row kernels read (unmasked).
+    deblur_ctx tmp;
+    tmp.N = n;
+    tmp.nt = batch;
+    std::vector<TileInfo> ti(batch);
+    for (int t = 0; t < batch; ++t) {
+        ti[t] = TileInfo{};
+        ti[t].sy = ti[t].sx = ti[t].by = ti[t].bx = n;
+        ti[t].nky = ti[t].nkx = 1;
+    }
+    std::vector<float> ones((size_t)dbl::kMaxK * n, 1.0f);
+    std::vector<float2> tw(n);
+    for (int e = 0; e < n; ++e) {
+        const double a = -2.0 * M_PI * (double)e / n;
+        tw[e] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    int rc = dev_alloc(&tmp, &tmp.tiles, batch);
+    if (!rc) rc = dev_alloc(&tmp, &tmp.tentX, ones.size());
+    if (!rc) rc = dev_alloc(&tmp, &tmp.tw, tw.size());
+    hipError_t e = hipSuccess;
+    if (!rc) {
+        e = hipMemcpy(tmp.tiles, ti.data(), batch * sizeof(TileInfo), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(tmp.tentX, ones.data(), ones.size() * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(tmp.tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice);
+    }
+    if (!rc && e == hipSuccess) {
+        if (which == 0) {
+            row_fwd(&tmp, s, in, reinterpret_cast<float2*>(out), 0);
+        } else if (which == 3) {
+            row_inv(&tmp, s, reinterpret_cast<const float2*>(in), out, 0);
+        } else {
+            DISPATCH_N(&tmp, launch_col_fft_dbg, s, reinterpret_cast<const float2*>(in),
+                       reinterpret_cast<float2*>(out), which == 1 ? -1 : 1);
+        }
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    for (void* p : tmp.allocs) (void)hipFree(p);
+    tmp.allocs.clear();
+    if (rc) return fail(nullptr, rc, tmp.err);
+    if (e != hipSuccess) return fail(nullptr, DEBLUR_E_HIP, hipGetErrorString(e));
+    return DEBLUR_OK;
+}
+
+}  // extern "C"

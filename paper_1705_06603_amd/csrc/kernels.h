@@ -1,0 +1,986 @@
+// Device kernels of the batched tile solver.
+//
+// Every tile t keeps its unknowns in an N x N frame (N in {160, 320, 640}):
+// frame pixel (m, c) is the support pixel (m, c) for m < support_h and
+// c < support_w, zero elsewhere.  The forward operator of Section II-B is a
+// circular convolution on the frame followed by a chop to the block, frame
+// rows/columns [r, r + block): any N >= support makes that exact.
+//
+// Spectra use a packed half-plane stored column-major, [f][g] with
+// f in [0, N/2) (row frequency) and g in [0, N) (column frequency): the
+// row transform of a real frame is taken as a length-N/2 complex FFT of
+// (even + i odd) samples, its DC and Nyquist values (both real) share slot
+// f = 0 as DC + i Nyquist, and the column transform runs along g.  PSF
+// spectra are stored with N/2 + 1 columns: for f in [1, N/2) the plain 2-D
+// DFT scaled by 2/N^2, for f = 0 the pair c1 = (H(g,0) + H(g,N/2))/2 (column
+// 0) and c2 = (H(g,0) - H(g,N/2))/2 (column N/2), so that the packed column
+// obeys  Y0(g) = c1(g) Z0(g) + c2(g) conj(Z0(-g)).
+//
+// One Local-Solver step is four kernels:
+//   col_H      : sum over terms of column FFT(a_ky . Z_kx) x spectrum, inverse column FFT
+//   row_resid  : row C2R -> H x, residual W (H x - y) on the block, its row R2C
+//   col_Ht     : column FFT, x conj spectrum per term, inverse column FFT, sum_ky a_ky
+//   row_update : row C2R per kx, sum_kx b_kx -> H^T r, + lambda grad phi + alpha (x - u),
+//                projected step, then the masked row R2Cs of the new x for the next step
+// with a_ky / b_kx the separable PSF-interpolation weights w_k = a_ky(row) b_kx(col).
+#pragma once
+
+#include "fft_core.h"
+
+namespace dbl {
+
+constexpr int kMaxK = 3;   // PSF terms per axis and tile
+
+struct TileInfo {
+    int ty, tx;        // tile grid position
+    int sy, sx;        // support size
+    int by, bx;        // block size
+    int nky, nkx;      // terms per axis
+    int spec[kMaxK * kMaxK];   // spectrum index of term (ky, kx) at ky * 3 + kx
+};
+
+struct Cover {         // tiles covering one X row (or column)
+    int a0, m0, a1, m1;   // tile index and frame coordinate; a1 < 0 if only one
+    float w0, w1;         // consensus weights omega
+    int pad0, pad1;
+};
+
+struct SolveParams {
+    float lambda, reg_param, gamma, rho;
+    int reg, bc, positivity, r;
+};
+
+template <int N> struct Cfg {
+    static constexpr int n = N / 2;          // complex length of a row transform
+    static constexpr int LwR = kPts / n;     // rows per wave
+    static constexpr int LwC = kPts / N;     // columns per wave
+    static constexpr int W = (N == 160) ? 2 : 4;   // waves per workgroup
+    static constexpr int NT = W * kLanes;
+    static constexpr int RB = W * LwR;       // rows per row workgroup
+    static constexpr int CB = W * LwC;       // columns per column workgroup
+    static constexpr int RG = N / RB;        // row workgroups per tile
+    static constexpr int CG = (N / 2) / CB;  // column workgroups per tile
+    static constexpr int LSR = n + 1;
+    static constexpr int LSC = N + 1;
+    static constexpr size_t SPEC = (size_t)(N / 2) * N;   // complex values of one half-plane
+    static constexpr size_t NSPEC = (size_t)(N / 2 + 1) * N;
+    static_assert(RG * RB == N && CG * CB == N / 2, "frame does not split into workgroups");
+};
+
+// ---------------------------------------------------------------------------
+// Row transforms (workgroup level)
+// ---------------------------------------------------------------------------
+
+// Transposed store of the WG's rows (natural-order row FFTs of the packed
+// real rows, in sbuf) as packed half-spectra out[f][i0 + row].
+template <int N>
+__device__ __forceinline__ void store_spectrum_T(const float2* __restrict__ sbuf, const float2* __restrict__ tw,
+                                                 float2* __restrict__ out, int i0, int tid) {
+    using C = Cfg<N>;
+    constexpr int n = C::n;
+#pragma unroll 4
+    for (int e = tid; e < C::RB * n; e += C::NT) {
+        const int row = e % C::RB, f = e / C::RB;
+        const float2 Z = sbuf[row * C::LSR + f];
+        float2 P;
+        if (f == 0) {
+            P = make_float2(Z.x + Z.y, Z.x - Z.y);
+        } else {
+            const float2 Zm = sbuf[row * C::LSR + (n - f)];
+            // X = (Z + conj Zm)/2 - i W_N^f (Z - conj Zm)/2
+            const float2 A = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
+            const float2 B = make_float2(0.5f * (Z.x - Zm.x), 0.5f * (Z.y + Zm.y));
+            const float2 wB = cmul(tw[f], B);
+            P = make_float2(A.x + wB.y, A.y - wB.x);
+        }
+        out[(size_t)f * N + i0 + row] = P;
+    }
+}
+
+// Transposed load of packed half-spectra in[f][i0 + row] into sbuf[row][f].
+template <int N>
+__device__ __forceinline__ void load_spectrum_T(float2* __restrict__ sbuf, const float2* __restrict__ in,
+                                                int i0, int tid) {
+    using C = Cfg<N>;
+    constexpr int n = C::n;
+#pragma unroll 4
+    for (int e = tid; e < C::RB * n; e += C::NT) {
+        const int row = e % C::RB, f = e / C::RB;
+        sbuf[row * C::LSR + f] = in[(size_t)f * N + i0 + row];
+    }
+}
+
+// Wave-level C2R of the wave's rows held in sw (packed half-spectra, natural
+// order).  Result: v[s] = (x[2m], x[2m+1]) in layout L5 of length n, i.e.
+// times N/2 relative to the normalised inverse (folded into the spectra).
+template <int N>
+__device__ __forceinline__ void row_c2r_wave(float2 (&v)[kV], float2* __restrict__ sw,
+                                             const float2* __restrict__ tw, int lane) {
+    using C = Cfg<N>;
+    constexpr int n = C::n;
+    constexpr int R0 = first_radix<n, kInv>();
+#pragma unroll
+    for (int s = 0; s < kV; ++s) {
+        int q, f;
+        slot_pos<n, R0>(lane, s, q, f);
+        const float2 X = sw[q * C::LSR + f];
+        if (f == 0) {
+            v[s] = make_float2(0.5f * (X.x + X.y), 0.5f * (X.x - X.y));
+        } else {
+            const float2 Xm = sw[q * C::LSR + (n - f)];
+            const float2 E = make_float2(0.5f * (X.x + Xm.x), 0.5f * (X.y - Xm.y));
+            const float2 D = make_float2(0.5f * (X.x - Xm.x), 0.5f * (X.y + Xm.y));
+            const float2 O = cmulc(D, tw[f]);          // D * W_N^{-f}
+            v[s] = make_float2(E.x - O.y, E.y + O.x);   // E + i O
+        }
+    }
+    wave_sync();
+    fft_passes<n, kInv, 2>(v, sw, tw, lane);
+}
+
+// Wave-level forward row FFT of v (layout L5 of length n, packed real pairs)
+// into sw in natural order.
+template <int N>
+__device__ __forceinline__ void row_fft_wave(float2 (&v)[kV], float2* __restrict__ sw,
+                                             const float2* __restrict__ tw, int lane) {
+    constexpr int n = Cfg<N>::n;
+    fft_passes<n, kFwd, 2>(v, sw, tw, lane);
+    wave_sync();
+    store_natural<n, last_radix<n, kFwd>()>(v, sw, lane);
+}
+
+template <int N>
+__device__ __forceinline__ void load_twiddles(float2* __restrict__ tw, const float2* __restrict__ twg, int tid) {
+    for (int e = tid; e < N; e += Cfg<N>::NT) tw[e] = twg[e];
+}
+
+// x (frames) -> packed row half-spectra of b_k . x for each mask k of the
+// tile (masked != 0) or of x itself (masked == 0, one output).
+template <int N>
+__global__ __launch_bounds__(Cfg<N>::NT) void k_row_fwd(const float* __restrict__ x, const TileInfo* __restrict__ tiles,
+                                                        const float* __restrict__ tentX, const float2* __restrict__ twg,
+                                                        float2* __restrict__ out, int masked) {
+    using C = Cfg<N>;
+    constexpr int n = C::n;
+    __shared__ float2 sbuf[C::RB * C::LSR];
+    __shared__ float2 tw[N];
+    const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    load_twiddles<N>(tw, twg, tid);
+    const TileInfo ti = tiles[t];
+    const int nk = masked ? ti.nkx : 1;
+    const int kstride = masked ? kMaxK : 1;
+    const float* xt = x + (size_t)t * N * N;
+    float2 xv[kV];
+#pragma unroll
+    for (int s = 0; s < kV; ++s) {
+        int q, m;
+        slot_pos<n, 5>(lane, s, q, m);
+        const int row = i0 + wave * C::LwR + q;
+        xv[s] = *reinterpret_cast<const float2*>(xt + (size_t)row * N + 2 * m);
+    }
+    __syncthreads();
+    float2* sw = sbuf + wave * C::LwR * C::LSR;
+    for (int k = 0; k < nk; ++k) {
+        float2 v[kV];
+        const float* bm = tentX + ((size_t)ti.tx * kMaxK + k) * N;
+#pragma unroll
+        for (int s = 0; s < kV; ++s) {
+            int q, m;
+            slot_pos<n, 5>(lane, s, q, m);
+            v[s] = masked ? make_float2(bm[2 * m] * xv[s].x, bm[2 * m + 1] * xv[s].y) : xv[s];
+        }
+        row_fft_wave<N>(v, sw, tw, lane);
+        __syncthreads();
+        store_spectrum_T<N>(sbuf, tw, out + ((size_t)t * kstride + k) * C::SPEC, i0, tid);
+        __syncthreads();
+    }
+}
+
+// Packed row half-spectra -> real frames: out = sum_k b_k . C2R(in_k)
+// (masked != 0) or C2R(in_0) (masked == 0).
+template <int N>
+__global__ __launch_bounds__(Cfg<N>::NT) void k_row_inv(const float2* __restrict__ in, const TileInfo* __restrict__ tiles,
+                                                        const float* __restrict__ tentX, const float2* __restrict__ twg,
+                                                        float* __restrict__ out, int masked) {
+    using C = Cfg<N>;
+    constexpr int n = C::n;
+    __shared__ float2 sbuf[C::RB * C::LSR];
+    __shared__ float2 tw[N];
+    const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    load_twiddles<N>(tw, twg, tid);
+    const TileInfo ti = tiles[t];
+    const int nk = masked ? ti.nkx : 1;
+    const int kstride = masked ? kMaxK : 1;
+    float2* sw = sbuf + wave * C::LwR * C::LSR;
+    float2 acc[kV];
+#pragma unroll
+    for (int s = 0; s < kV; ++s) acc[s] = make_float2(0.f, 0.f);
+    for (int k = 0; k < nk; ++k) {
+        __syncthreads();
+        load_spectrum_T<N>(sbuf, in + ((size_t)t * kstride + k) * C::SPEC, i0, tid);
+        __syncthreads();
+        float2 v[kV];
+        row_c2r_wave<N>(v, sw, tw, lane);
+        const float* bm = tentX + ((size_t)ti.tx * kMaxK + k) * N;
+#pragma unroll
+        for (int s = 0; s < kV; ++s) {
+            int q, m;
+            slot_pos<n, 5>(lane, s, q, m);
+            if (masked) {
+                acc[s].x += bm[2 * m] * v[s].x;
+                acc[s].y += bm[2 * m + 1] * v[s].y;
+            } else {
+                acc[s] = v[s];
+            }
+        }
+    }
+    float* ot = out + (size_t)t * N * N;
+#pragma unroll
+    for (int s = 0; s < kV; ++s) {
+        int q, m;
+        slot_pos<n, 5>(lane, s, q, m);
+        const int row = i0 + wave * C::LwR + q;
+        *reinterpret_cast<float2*>(ot + (size_t)row * N + 2 * m) = acc[s];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column kernels
+// ---------------------------------------------------------------------------
+
+// H: Yc[f][:] = IFFT_col( sum_{ky,kx} spec_k . FFT_col(a_ky . Z_kx[f][:]) )
+template <int N>
+__global__ __launch_bounds__(Cfg<N>::NT) void k_col_H(const float2* __restrict__ Zk, const TileInfo* __restrict__ tiles,
+                                                      const float* __restrict__ tentY, const float2* __restrict__ spec,
+                                                      const float2* __restrict__ twg, float2* __restrict__ Yc) {
+    using C = Cfg<N>;
+    constexpr int RL = last_radix<N, kFwd>();
+    __shared__ float2 lds[C::W * C::LwC * C::LSC];
+    __shared__ float2 tw[N];
+    __shared__ float2 col0[N];
+    const int t = blockIdx.y;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int f0 = blockIdx.x * C::CB + wave * C::LwC;
+    load_twiddles<N>(tw, twg, tid);
+    __syncthreads();
+    const TileInfo ti = tiles[t];
+    float2* sw = lds + wave * C::LwC * C::LSC;
+    float2 acc[kV];
+#pragma unroll
+    for (int s = 0; s < kV; ++s) acc[s] = make_float2(0.f, 0.f);
+    for (int kx = 0; kx < ti.nkx; ++kx) {
+        const float2* zt = Zk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)f0 * N;
+        float2 zin[kV];
+#pragma unroll
+        for (int s = 0; s < kV; ++s) {
+            int q, g;
+            slot_pos<N, 5>(lane, s, q, g);
+            zin[s] = zt[(size_t)q * N + g];
+        }
+        for (int ky = 0; ky < ti.nky; ++ky) {
+            const float* am = tentY + ((size_t)ti.ty * kMaxK + ky) * N;
+            float2 v[kV];
+#pragma unroll
+            for (int s = 0; s < kV; ++s) {
+                int q, g;
+                slot_pos<N, 5>(lane, s, q, g);
+                v[s] = cscale(zin[s], am[g]);
+            }
+            fft_passes<N, kFwd, 1>(v, sw, tw, lane);
+            const float2* sp = spec + (size_t)tiles[t].spec[ky * kMaxK + kx] * C::NSPEC;
+            if (f0 == 0) {
+#pragma unroll
+                for (int s = 0; s < kV; ++s) {
+                    int q, g;
+                    slot_pos<N, RL>(lane, s, q, g);
+                    if (q == 0) col0[g] = v[s];
+                }
+                wave_sync();
+#pragma unroll
+                for (int s = 0; s < kV; ++s) {
+                    int q, g;
+                    slot_pos<N, RL>(lane, s, q, g);
+                    if (q == 0) {
+                        const float2 vm = col0[(N - g) % N];
+                        acc[s] = cadd(acc[s], cadd(cmul(sp[g], v[s]), cmul(sp[(size_t)(N / 2) * N + g], cconj(vm))));
+                    } else {
+                        acc[s] = cadd(acc[s], cmul(sp[(size_t)q * N + g], v[s]));
+                    }
+                }
+                wave_sync();
+            } else {
+#pragma unroll
+                for (int s = 0; s < kV; ++s) {
+                    int q, g;
+                    slot_pos<N, RL>(lane, s, q, g);
+                    acc[s] = cadd(acc[s], cmul(sp[(size_t)(f0 + q) * N + g], v[s]));
+                }
+            }
+        }
+    }
+    fft_passes<N, kInv, 1>(acc, sw, tw, lane);
+    float2* yt = Yc + (size_t)t * C::SPEC + (size_t)f0 * N;
+#pragma unroll
+    for (int s = 0; s < kV; ++s) {
+        int q, g;
+        slot_pos<N, 5>(lane, s, q, g);
+        yt[(size_t)q * N + g] = acc[s];
+    }
+}
+
+// H^T: Gk[kx][f][:] = sum_ky a_ky . IFFT_col( conj(spec_k) . FFT_col(Rr[f][:]) )
+template <int N>
+__global__ __launch_bounds__(Cfg<N>::NT) void k_col_Ht(const float2* __restrict__ Rr, const TileInfo* __restrict__ tiles,
+                                                       const float* __restrict__ tentY, const float2* __restrict__ spec,
+                                                       const float2* __restrict__ twg, float2* __restrict__ Gk) {
+    using C = Cfg<N>;
+    constexpr int RL = last_radix<N, kFwd>();
+    __shared__ float2 lds[C::W * C::LwC * C::LSC];
+    __shared__ float2 tw[N];
+    __shared__ float2 col0[N];
+    const int t = blockIdx.y;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int f0 = blockIdx.x * C::CB + wave * C::LwC;
+    load_twiddles<N>(tw, twg, tid);
+    __syncthreads();
+    const TileInfo ti = tiles[t];
+    float2* sw = lds + wave * C::LwC * C::LSC;
+    float2 S[kV];
+    {
+        const float2* rt = Rr + (size_t)t * C::SPEC + (size_t)f0 * N;
+#pragma unroll
+        for (int s = 0; s < kV; ++s) {
+            int q, g;
+            slot_pos<N, 5>(lane, s, q, g);
+            S[s] = rt[(size_t)q * N + g];
+        }
+    }
+    fft_passes<N, kFwd, 1>(S, sw, tw, lane);
+    if (f0 == 0) {
+#pragma unroll
+        for (int s = 0; s < kV; ++s) {
+            int q, g;
+            slot_pos<N, RL>(lane, s, q, g);
+            if (q == 0) col0[g] = S[s];
+        }
+        wave_sync();
+    }
+    for (int kx = 0; kx < ti.nkx; ++kx) {
+        float2 acc[kV];
+#pragma unroll
+        for (int s = 0; s < kV; ++s) acc[s] = make_float2(0.f, 0.f);
+        for (int ky = 0; ky < ti.nky; ++ky) {
+            const float2* sp = spec + (size_t)tiles[t].spec[ky * kMaxK + kx] * C::NSPEC;
+            float2 v[kV];
+#pragma unroll
+            for (int s = 0; s < kV; ++s) {
+                int q, g;
+                slot_pos<N, RL>(lane, s, q, g);
+                if (f0 == 0 && q == 0) {
+                    const float2 Sm = col0[(N - g) % N];
+                    v[s] = cadd(cmulc(S[s], sp[g]), cmulc(cconj(Sm), sp[(size_t)(N / 2) * N + g]));
+                } else {
+                    v[s] = cmulc(S[s], sp[(size_t)(f0 + q) * N + g]);
+                }
+            }
+            fft_passes<N, kInv, 1>(v, sw, tw, lane);
+            const float* am = tentY + ((size_t)ti.ty * kMaxK + ky) * N;
+#pragma unroll
+            for (int s = 0; s < kV; ++s) {
+                int q, g;
+                slot_pos<N, 5>(lane, s, q, g);
+                acc[s] = cadd(acc[s], cscale(v[s], am[g]));
+            }
+        }
+        float2* gt = Gk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)f0 * N;
+#pragma unroll
+        for (int s = 0; s < kV; ++s) {
+            int q, g;
+            slot_pos<N, 5>(lane, s, q, g);
+            gt[(size_t)q * N + g] = acc[s];
+        }
+    }
+}
+
+// Diagnostic: forward (dir < 0) or unnormalised inverse (dir > 0) FFT of every
+// column in[t][f][:] of packed half-planes.
+template <int N>
+__global__ __launch_bounds__(Cfg<N>::NT) void k_col_fft_dbg(const float2* __restrict__ in, const float2* __restrict__ twg,
+                                                            float2* __restrict__ out, int dir) {
+    using C = Cfg<N>;
+    __shared__ float2 lds[C::W * C::LwC * C::LSC];
+    __shared__ float2 tw[N];
+    const int t = blockIdx.y;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int f0 = blockIdx.x * C::CB + wave * C::LwC;
+    load_twiddles<N>(tw, twg, tid);
+    __syncthreads();
+    float2* sw = lds + wave * C::LwC * C::LSC;
+    const float2* it = in + (size_t)t * C::SPEC + (size_t)f0 * N;
+    float2* ot = out + (size_t)t * C::SPEC + (size_t)f0 * N;
+    float2 v[kV];
+    if (dir < 0) {
+#pragma unroll
+        for (int s = 0; s < kV; ++s) {
+            int q, g;
+            slot_pos<N, first_radix<N, kFwd>()>(lane, s, q, g);
+            v[s] = it[(size_t)q * N + g];
+        }
+        fft_passes<N, kFwd, 1>(v, sw, tw, lane);
+#pragma unroll
+        for (int s = 0; s < kV; ++s) {
+            int q, g;
+            slot_pos<N, last_radix<N, kFwd>()>(lane, s, q, g);
+            ot[(size_t)q * N + g] = v[s];
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < kV; ++s) {
+            int q, g;
+            slot_pos<N, first_radix<N, kInv>()>(lane, s, q, g);
+            v[s] = it[(size_t)q * N + g];
+        }
+        fft_passes<N, kInv, 1>(v, sw, tw, lane);
+#pragma unroll
+        for (int s = 0; s < kV; ++s) {
+            int q, g;
+            slot_pos<N, last_radix<N, kInv>()>(lane, s, q, g);
+            ot[(size_t)q * N + g] = v[s];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused row kernels of the Local-Solver step
+// ---------------------------------------------------------------------------
+
+template <int N>
+__device__ __forceinline__ float block_sum(float v, float* red, int tid) {
+    using C = Cfg<N>;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    float s = 0.f;
+    if (tid == 0) {
+        for (int w = 0; w < C::W; ++w) s += red[w];
+    }
+    return s;   // valid in thread 0
+}
+
+// H x (from Yc) -> residual W (H x - y) on the block -> its packed row spectra.
+// obj_part[t * RG + rg] = 1/2 sum W (H x - y)^2 over the workgroup's rows.
+template <int N>
+__global__ __launch_bounds__(Cfg<N>::NT) void k_row_resid(const float2* __restrict__ Yc, const float2* __restrict__ yw,
+                                                          const float2* __restrict__ twg, float2* __restrict__ Rr,
+                                                          float* __restrict__ obj_part) {
+    using C = Cfg<N>;
+    constexpr int n = C::n;
+    __shared__ float2 sbuf[C::RB * C::LSR];
+    __shared__ float2 tw[N];
+    __shared__ float red[C::W];
+    const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    load_twiddles<N>(tw, twg, tid);
+    load_spectrum_T<N>(sbuf, Yc + (size_t)t * C::SPEC, i0, tid);
+    __syncthreads();
+    float2* sw = sbuf + wave * C::LwR * C::LSR;
+    float2 v[kV];
+    row_c2r_wave<N>(v, sw, tw, lane);
+    const float4* ywt = reinterpret_cast<const float4*>(yw + (size_t)t * N * N);
+    float obj = 0.f;
+#pragma unroll
+    for (int s = 0; s < kV; ++s) {
+        int q, m;
+        slot_pos<n, 5>(lane, s, q, m);
+        const int row = i0 + wave * C::LwR + q;
+        const float4 o = ywt[((size_t)row * N + 2 * m) >> 1];   // (y0, W0, y1, W1)
+        const float d0 = v[s].x - o.x, d1 = v[s].y - o.z;
+        const float r0 = o.y * d0, r1 = o.w * d1;
+        obj += r0 * d0 + r1 * d1;
+        v[s] = make_float2(r0, r1);
+    }
+    wave_sync();
+    row_fft_wave<N>(v, sw, tw, lane);
+    __syncthreads();
+    store_spectrum_T<N>(sbuf, tw, Rr + (size_t)t * C::SPEC, i0, tid);
+    const float tot = block_sum<N>(obj, red, tid);
+    if (tid == 0) obj_part[t * C::RG + blockIdx.x] = 0.5f * tot;
+}
+
+// Gradient of the regulariser at support pixel (i, c) of frame xt.
+__device__ __forceinline__ float reg_grad(const float* __restrict__ xt, int N, int i, int c, int sy, int sx,
+                                          const SolveParams& P) {
+    const bool circ = P.bc != 0;
+    auto X = [&](int a, int b) { return xt[(size_t)a * N + b]; };
+    auto q = [&](int a, int b, float& qh, float& qv) {
+        const float x0 = X(a, b);
+        float gh, gv;
+        if (circ) {
+            gh = X(a, b + 1 < sx ? b + 1 : 0) - x0;
+            gv = X(a + 1 < sy ? a + 1 : 0, b) - x0;
+        } else {
+            gh = (b + 1 < sx) ? X(a, b + 1) - x0 : 0.f;
+            gv = (a + 1 < sy) ? X(a + 1, b) - x0 : 0.f;
+        }
+        const float n2 = gh * gh + gv * gv;
+        float sc;
+        if (P.reg == 0) sc = 1.0f / sqrtf(n2 + P.reg_param * P.reg_param);
+        else sc = P.reg_param / fmaxf(sqrtf(n2), P.reg_param);
+        qh = sc * gh;
+        qv = sc * gv;
+    };
+    float qh, qv, g;
+    q(i, c, qh, qv);
+    g = -qh - qv;
+    if (c >= 1 || circ) {
+        float a, b;
+        q(i, c >= 1 ? c - 1 : sx - 1, a, b);
+        g += a;
+    }
+    if (i >= 1 || circ) {
+        float a, b;
+        q(i >= 1 ? i - 1 : sy - 1, c, a, b);
+        g += b;
+    }
+    return g;
+}
+
+// H^T r (from Gk), regulariser and metric terms, projected step; then the
+// masked row spectra of the new iterate for the next step.
+template <int N>
+__global__ __launch_bounds__(Cfg<N>::NT) void k_row_update(
+        const float2* __restrict__ Gk, const float* __restrict__ xc, const float* __restrict__ u,
+        const TileInfo* __restrict__ tiles, const float* __restrict__ tentX, const float* __restrict__ omY,
+        const float* __restrict__ omX, const float* __restrict__ tau, SolveParams P,
+        const float2* __restrict__ twg, float* __restrict__ xn, float2* __restrict__ Zk) {
+    using C = Cfg<N>;
+    constexpr int n = C::n;
+    __shared__ float2 sbuf[C::RB * C::LSR];
+    __shared__ float2 tw[N];
+    const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    load_twiddles<N>(tw, twg, tid);
+    const TileInfo ti = tiles[t];
+    float2* sw = sbuf + wave * C::LwR * C::LSR;
+    float2 gd[kV];
+#pragma unroll
+    for (int s = 0; s < kV; ++s) gd[s] = make_float2(0.f, 0.f);
+    for (int kx = 0; kx < ti.nkx; ++kx) {
+        __syncthreads();
+        load_spectrum_T<N>(sbuf, Gk + ((size_t)t * kMaxK + kx) * C::SPEC, i0, tid);
+        __syncthreads();
+        float2 v[kV];
+        row_c2r_wave<N>(v, sw, tw, lane);
+        const float* bm = tentX + ((size_t)ti.tx * kMaxK + kx) * N;
+#pragma unroll
+        for (int s = 0; s < kV; ++s) {
+            int q, m;
+            slot_pos<n, 5>(lane, s, q, m);
+            gd[s].x += bm[2 * m] * v[s].x;
+            gd[s].y += bm[2 * m + 1] * v[s].y;
+        }
+    }
+    const float* xt = xc + (size_t)t * N * N;
+    const float* ut = u + (size_t)t * N * N;
+    float* xo = xn + (size_t)t * N * N;
+    const float tt = tau[t];
+    const float* oy = omY + (size_t)ti.ty * N;
+    const float* ox = omX + (size_t)ti.tx * N;
+    float2 xv[kV];
+#pragma unroll
+    for (int s = 0; s < kV; ++s) {
+        int q, m;
+        slot_pos<n, 5>(lane, s, q, m);
+        const int i = i0 + wave * C::LwR + q;
+        float out[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = 2 * m + h;
+            float val = 0.f;
+            if (i < ti.sy && c < ti.sx) {
+                const float x0 = xt[(size_t)i * N + c];
+                const float alpha = P.gamma * oy[i] * ox[c];
+                const float g = (h ? gd[s].y : gd[s].x) + P.lambda * reg_grad(xt, N, i, c, ti.sy, ti.sx, P) +
+                                alpha * (x0 - ut[(size_t)i * N + c]);
+                val = x0 - tt * g;
+                if (P.positivity) val = fmaxf(val, 0.f);
+            }
+            out[h] = val;
+        }
+        xv[s] = make_float2(out[0], out[1]);
+        *reinterpret_cast<float2*>(xo + (size_t)i * N + 2 * m) = xv[s];
+    }
+    for (int kx = 0; kx < ti.nkx; ++kx) {
+        const float* bm = tentX + ((size_t)ti.tx * kMaxK + kx) * N;
+        float2 v[kV];
+#pragma unroll
+        for (int s = 0; s < kV; ++s) {
+            int q, m;
+            slot_pos<n, 5>(lane, s, q, m);
+            v[s] = make_float2(bm[2 * m] * xv[s].x, bm[2 * m + 1] * xv[s].y);
+        }
+        __syncthreads();
+        row_fft_wave<N>(v, sw, tw, lane);
+        __syncthreads();
+        store_spectrum_T<N>(sbuf, tw, Zk + ((size_t)t * kMaxK + kx) * C::SPEC, i0, tid);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Consensus, assembly and bookkeeping (one thread per pixel of X)
+// ---------------------------------------------------------------------------
+
+constexpr int kPixBlock = 256;
+
+__device__ __forceinline__ float2 block_sum2(float2 v, float2* red, int tid) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x += __shfl_xor(v.x, o, 64);
+        v.y += __shfl_xor(v.y, o, 64);
+    }
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    float2 s = make_float2(0.f, 0.f);
+    if (tid == 0) {
+        for (int w = 0; w < kPixBlock / 64; ++w) {
+            s.x += red[w].x;
+            s.y += red[w].y;
+        }
+    }
+    return s;
+}
+
+// zbar = sum omega (2x - u) / sum omega over covering tiles; u += rho (zbar - x).
+// part[block] = (sum (u_new - u_old)^2, sum u_new^2) over the pixels' tile copies.
+__global__ __launch_bounds__(kPixBlock) void k_consensus(const float* __restrict__ x, float* __restrict__ u,
+                                                        const Cover* __restrict__ cy, const Cover* __restrict__ cx,
+                                                        int Xy, int Xx, int Tx, int N, float rho,
+                                                        float2* __restrict__ part) {
+    __shared__ float2 red[kPixBlock / 64];
+    const int tid = threadIdx.x;
+    const int J = blockIdx.x * kPixBlock + tid, I = blockIdx.y;
+    float du2 = 0.f, un2 = 0.f;
+    if (J < Xx) {
+        const Cover a = cy[I], b = cx[J];
+        const int na = a.a1 >= 0 ? 2 : 1, nb = b.a1 >= 0 ? 2 : 1;
+        size_t idx[4];
+        float xv[4], uv[4];
+        float num = 0.f, den = 0.f;
+        int k = 0;
+        for (int ia = 0; ia < na; ++ia) {
+            const int ta = ia ? a.a1 : a.a0, m = ia ? a.m1 : a.m0;
+            const float wa = ia ? a.w1 : a.w0;
+            for (int ib = 0; ib < nb; ++ib) {
+                const int tb = ib ? b.a1 : b.a0, c = ib ? b.m1 : b.m0;
+                const float w = wa * (ib ? b.w1 : b.w0);
+                idx[k] = ((size_t)(ta * Tx + tb) * N + m) * N + c;
+                xv[k] = x[idx[k]];
+                uv[k] = u[idx[k]];
+                num += w * (2.f * xv[k] - uv[k]);
+                den += w;
+                ++k;
+            }
+        }
+        const float zb = num / den;
+        for (int j = 0; j < k; ++j) {
+            const float un = uv[j] + rho * (zb - xv[j]);
+            u[idx[j]] = un;
+            du2 += (un - uv[j]) * (un - uv[j]);
+            un2 += un * un;
+        }
+    }
+    const float2 s = block_sum2(make_float2(du2, un2), red, tid);
+    if (tid == 0) part[(size_t)I * gridDim.x + blockIdx.x] = s;
+}
+
+// Fixed-order reduction of the consensus partials into the residual
+// ||u_new - u_old|| / ||u_new||, written to hist[*counter] and *last.
+__global__ __launch_bounds__(256) void k_finalize_residual(const float2* __restrict__ part, int np,
+                                                          double* __restrict__ hist, int* __restrict__ counter,
+                                                          double* __restrict__ last, int cap) {
+    __shared__ double sa[256], sb[256];
+    const int tid = threadIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int i = tid; i < np; i += 256) {
+        a += (double)part[i].x;
+        b += (double)part[i].y;
+    }
+    sa[tid] = a;
+    sb[tid] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) {
+            sa[tid] += sa[tid + o];
+            sb[tid] += sb[tid + o];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double res = sb[0] > 0.0 ? sqrt(sa[0] / sb[0]) : 0.0;
+        const double out = (isfinite(sa[0]) && isfinite(sb[0])) ? res : (double)NAN;
+        *last = out;
+        const int k = *counter;
+        if (k < cap) hist[k] = out;
+        *counter = k + 1;
+    }
+}
+
+__global__ void k_set_int(int* p, int v) { *p = v; }
+
+// x_hat = sum omega x / sum omega on X.
+__global__ __launch_bounds__(kPixBlock) void k_assemble(const float* __restrict__ x, const Cover* __restrict__ cy,
+                                                       const Cover* __restrict__ cx, int Xx, int Tx, int N,
+                                                       float* __restrict__ out) {
+    const int J = blockIdx.x * kPixBlock + threadIdx.x, I = blockIdx.y;
+    if (J >= Xx) return;
+    const Cover a = cy[I], b = cx[J];
+    const int na = a.a1 >= 0 ? 2 : 1, nb = b.a1 >= 0 ? 2 : 1;
+    float num = 0.f, den = 0.f;
+    for (int ia = 0; ia < na; ++ia) {
+        const int ta = ia ? a.a1 : a.a0, m = ia ? a.m1 : a.m0;
+        const float wa = ia ? a.w1 : a.w0;
+        for (int ib = 0; ib < nb; ++ib) {
+            const int tb = ib ? b.a1 : b.a0, c = ib ? b.m1 : b.m0;
+            const float w = wa * (ib ? b.w1 : b.w0);
+            num += w * x[((size_t)(ta * Tx + tb) * N + m) * N + c];
+            den += w;
+        }
+    }
+    out[(size_t)I * Xx + J] = num / den;
+}
+
+// ---------------------------------------------------------------------------
+// Packing between user layouts and frames
+// ---------------------------------------------------------------------------
+
+struct PackDesc {        // per tile
+    int y0, x0;          // frame coordinate of the region's first pixel
+    int h, w;            // region size
+    long long off;       // float offset in the packed array
+};
+
+// frames[t] = region from packed (zero elsewhere in the frame)
+__global__ void k_pack(const float* __restrict__ packed, const PackDesc* __restrict__ d, int N,
+                       float* __restrict__ frames) {
+    const int t = blockIdx.y;
+    const PackDesc pd = d[t];
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += gridDim.x * blockDim.x) {
+        const int m = e / N - pd.y0, c = e % N - pd.x0;
+        float v = 0.f;
+        if (m >= 0 && m < pd.h && c >= 0 && c < pd.w) v = packed[pd.off + (long long)m * pd.w + c];
+        frames[(size_t)t * N * N + e] = v;
+    }
+}
+
+__global__ void k_unpack(const float* __restrict__ frames, const PackDesc* __restrict__ d, int N,
+                         float* __restrict__ packed) {
+    const int t = blockIdx.y;
+    const PackDesc pd = d[t];
+    const int tot = pd.h * pd.w;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += gridDim.x * blockDim.x) {
+        const int m = e / pd.w, c = e % pd.w;
+        packed[pd.off + e] = frames[(size_t)t * N * N + (size_t)(m + pd.y0) * N + (c + pd.x0)];
+    }
+}
+
+// Global image on X -> support frames (zero outside supports).
+__global__ void k_scatter_X(const float* __restrict__ xg, const TileInfo* __restrict__ tiles,
+                            const int* __restrict__ org, int Xx, int N, float* __restrict__ frames) {
+    const int t = blockIdx.y;
+    const TileInfo ti = tiles[t];
+    const int oy = org[2 * t], ox = org[2 * t + 1];   // X index of the support origin
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += gridDim.x * blockDim.x) {
+        const int m = e / N, c = e % N;
+        float v = 0.f;
+        if (m < ti.sy && c < ti.sx) v = xg[(size_t)(oy + m) * Xx + ox + c];
+        frames[(size_t)t * N * N + e] = v;
+    }
+}
+
+// Observed y (global) <- frames' block regions, each pixel from its owner tile.
+__global__ void k_gather_owner(const float* __restrict__ frames, int My, int Mx, int pitch, int Ty, int Tx, int N,
+                               int r, float* __restrict__ y) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x, i = blockIdx.y;
+    if (j >= Mx) return;
+    const int a = min(i / pitch, Ty - 1), b = min(j / pitch, Tx - 1);
+    const int m = i - a * pitch + r, c = j - b * pitch + r;
+    y[(size_t)i * Mx + j] = frames[((size_t)(a * Tx + b) * N + m) * N + c];
+}
+
+// (y, W) frames on the block region from the global observation.
+__global__ void k_set_obs(const float* __restrict__ y, const float* __restrict__ w, const TileInfo* __restrict__ tiles,
+                          const int* __restrict__ borg, int Mx, int N, int r, float2* __restrict__ yw) {
+    const int t = blockIdx.y;
+    const TileInfo ti = tiles[t];
+    const int by0 = borg[2 * t], bx0 = borg[2 * t + 1];   // observed coordinate of the block origin
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += gridDim.x * blockDim.x) {
+        const int m = e / N - r, c = e % N - r;
+        float2 v = make_float2(0.f, 0.f);
+        if (m >= 0 && m < ti.by && c >= 0 && c < ti.bx) {
+            const size_t g = (size_t)(by0 + m) * Mx + (bx0 + c);
+            v = make_float2(y[g], w ? w[g] : 1.0f);
+        }
+        yw[(size_t)t * N * N + e] = v;
+    }
+}
+
+// x0 = max(y, 0) at the nearest observed pixel, on the supports; u0 = x0.
+__global__ void k_init_observed(const float* __restrict__ y, const TileInfo* __restrict__ tiles,
+                                const int* __restrict__ sorg, int My, int Mx, int N, float* __restrict__ x,
+                                float* __restrict__ u) {
+    const int t = blockIdx.y;
+    const TileInfo ti = tiles[t];
+    const int sy0 = sorg[2 * t], sx0 = sorg[2 * t + 1];   // observed coordinate of the support origin
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < N * N; e += gridDim.x * blockDim.x) {
+        const int m = e / N, c = e % N;
+        float v = 0.f;
+        if (m < ti.sy && c < ti.sx) {
+            const int gi = min(max(sy0 + m, 0), My - 1), gj = min(max(sx0 + c, 0), Mx - 1);
+            v = fmaxf(y[(size_t)gi * Mx + gj], 0.f);
+        }
+        x[(size_t)t * N * N + e] = v;
+        u[(size_t)t * N * N + e] = v;
+    }
+}
+
+__global__ void k_copy(const float* __restrict__ a, float* __restrict__ b, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
+__global__ void k_fill(float* __restrict__ a, float v, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+// Per-tile maximum over the block region of a frame array (stride 1) or of the
+// W component of the (y, W) frames (stride 2, offset 1).
+__global__ __launch_bounds__(256) void k_block_max(const float* __restrict__ fr, int stride, int off,
+                                                  const TileInfo* __restrict__ tiles, int N, int r,
+                                                  float* __restrict__ out) {
+    __shared__ float red[256];
+    const int t = blockIdx.x;
+    const TileInfo ti = tiles[t];
+    float m = -INFINITY;
+    for (int e = threadIdx.x; e < ti.by * ti.bx; e += 256) {
+        const int i = e / ti.bx + r, c = e % ti.bx + r;
+        m = fmaxf(m, fr[((size_t)t * N * N + (size_t)i * N + c) * stride + off]);
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[t] = red[0];
+}
+
+// Regulariser value and metric term per tile and row block:
+// part[t * gridDim.x + blk] = (sum phi(D x), sum 1/2 alpha (x - u)^2).
+__global__ __launch_bounds__(256) void k_reg_terms(const float* __restrict__ x, const float* __restrict__ u,
+                                                  const TileInfo* __restrict__ tiles, const float* __restrict__ omY,
+                                                  const float* __restrict__ omX, int N, SolveParams P,
+                                                  double* __restrict__ part) {
+    __shared__ double ra[256], rb[256];
+    const int t = blockIdx.y;
+    const TileInfo ti = tiles[t];
+    const float* xt = x + (size_t)t * N * N;
+    const float* ut = u + (size_t)t * N * N;
+    double sa = 0.0, sb = 0.0;
+    const int rows_per = (ti.sy + gridDim.x - 1) / gridDim.x;
+    const int r0 = blockIdx.x * rows_per, r1 = min(ti.sy, r0 + rows_per);
+    for (int e = threadIdx.x; e < (r1 - r0) * ti.sx; e += 256) {
+        const int i = r0 + e / ti.sx, c = e % ti.sx;
+        const float x0 = xt[(size_t)i * N + c];
+        float gh, gv;
+        if (P.bc) {
+            gh = xt[(size_t)i * N + (c + 1 < ti.sx ? c + 1 : 0)] - x0;
+            gv = xt[(size_t)(i + 1 < ti.sy ? i + 1 : 0) * N + c] - x0;
+        } else {
+            gh = c + 1 < ti.sx ? xt[(size_t)i * N + c + 1] - x0 : 0.f;
+            gv = i + 1 < ti.sy ? xt[(size_t)(i + 1) * N + c] - x0 : 0.f;
+        }
+        const double n2 = (double)gh * gh + (double)gv * gv;
+        const double p = P.reg_param;
+        double phi;
+        if (P.reg == 0) {
+            phi = sqrt(n2 + p * p) - p;
+        } else {
+            const double nn = sqrt(n2);
+            phi = nn <= p ? 0.5 * n2 : p * (nn - 0.5 * p);
+        }
+        sa += phi;
+        const double d = (double)x0 - ut[(size_t)i * N + c];
+        sb += 0.5 * (double)P.gamma * omY[(size_t)ti.ty * N + i] * omX[(size_t)ti.tx * N + c] * d * d;
+    }
+    ra[threadIdx.x] = sa;
+    rb[threadIdx.x] = sb;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            ra[threadIdx.x] += ra[threadIdx.x + o];
+            rb[threadIdx.x] += rb[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * ((size_t)t * gridDim.x + blockIdx.x)] = ra[0];
+        part[2 * ((size_t)t * gridDim.x + blockIdx.x) + 1] = rb[0];
+    }
+}
+
+// PSF spectra by a direct 2-D DFT in fp64 (setup only).  For each node and
+// each stored column f in [0, N/2] and row frequency g:
+//   H(g, f) = sum_q h(q) exp(-2 pi i (g qy + f qx) / N), scaled by 2/N^2,
+// stored as described at the top of this file.  twd[k] = exp(-2 pi i k / N)
+// in fp64; dynamic LDS holds a copy (N double2).
+__global__ void k_psf_spectra(const float* __restrict__ psf, int P, int N, const double2* __restrict__ twd,
+                              float2* __restrict__ spec) {
+    extern __shared__ double2 tws[];
+    for (int e = threadIdx.x; e < N; e += blockDim.x) tws[e] = twd[e];
+    __syncthreads();
+    const int node = blockIdx.y;
+    const int r = P / 2;
+    const int nf = N / 2 + 1;
+    const float* h = psf + (size_t)node * P * P;
+    const double scale = 2.0 / ((double)N * N);
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nf * N; e += gridDim.x * blockDim.x) {
+        const int f = e / N, g = e % N;
+        auto dft = [&](int ff) {
+            double re = 0.0, im = 0.0;
+            for (int a = 0; a < P; ++a) {
+                const int qy = a - r;
+                int ph = (int)(((long long)g * qy) % N);
+                if (ph < 0) ph += N;
+                int phx = (int)(((long long)ff * (-r)) % N);
+                if (phx < 0) phx += N;
+                int p0 = ph + phx;
+                if (p0 >= N) p0 -= N;
+                for (int b = 0; b < P; ++b) {
+                    const double2 w = tws[p0];
+                    const double hv = h[a * P + b];
+                    re += hv * w.x;
+                    im += hv * w.y;
+                    p0 += ff;
+                    if (p0 >= N) p0 -= N;
+                }
+            }
+            return make_double2(re * scale, im * scale);
+        };
+        float2 out;
+        if (f == 0 || f == N / 2) {
+            const double2 h0 = dft(0), hn = dft(N / 2);
+            const double sgn = (f == 0) ? 1.0 : -1.0;
+            out = make_float2((float)(0.5 * (h0.x + sgn * hn.x)), (float)(0.5 * (h0.y + sgn * hn.y)));
+        } else {
+            const double2 v = dft(f);
+            out = make_float2((float)v.x, (float)v.y);
+        }
+        spec[(size_t)node * nf * N + (size_t)f * N + g] = out;
+    }
+}
+
+}  // namespace dbl
