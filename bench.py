@@ -1,0 +1,221 @@
+"""Benchmark of the batched tile solve on one MI355X.
+
+One step = one full solve of the batched workload: 2048 x 2048 observed
+image in 8 x 8 tiles (32-px overlap, uneven edge tiles), 8 x 8 grid of 31 x 31
+Moffat PSFs, Poisson + read noise, smoothed TV, positivity, 200 Local-Solver
+iterations (20 D-R rounds of 10), i.e. init -> 20 graph-captured rounds ->
+output assembly.  Inputs (observation, weights, PSF spectra) are resident in
+HBM before the timed region starts.
+
+Prints one JSON line (see the keys below).  --gpus N > 1 is rejected: the
+solver runs every tile of the image on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Mpixel-iterations/s of tile solve; time to 1e-4 residual, warm-start vs plain"
+UNIT = "Mpixel-iterations/s"
+KERNELS_PER_STEP = ("col_H", "row_resid", "col_Ht", "row_update")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fft_core.h", "kernels.h"):
+        with open(os.path.join(ROOT, "paper_1705_06603_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def build_workload(seed_offset=0):
+    """Scene, PSFs and the noisy observation of the batched workload.
+
+    The blur is applied by the HIP library itself (deblur_blur_global);
+    noise and weights come from the seeded generators."""
+    import torch
+    from paper_1705_06603_amd import _lib as dl
+    from paper_1705_06603_amd import workloads
+
+    w = workloads.WORKLOADS["batched"]
+    scene, psfs = workloads.make_workload(w)
+    params = dl.make_params(w.M, w.tiles, w.pitch, w.overlap, w.grid, w.psf_size,
+                            lam=w.lam, reg_param=w.eps, gamma=w.gamma, rho=w.rho)
+    ctx = dl.Context(params, psfs)
+    x_dev = torch.tensor(scene.astype(np.float32), device="cuda")
+    blurred = ctx.blur_global(x_dev).cpu().numpy().astype(np.float64)
+    y, W = workloads.observe(blurred, w.noise, w.seed)
+    ctx.set_observation(torch.tensor(y.astype(np.float32), device="cuda"),
+                        torch.tensor(W.astype(np.float32), device="cuda"))
+    return ctx, w, scene, psfs, y, W
+
+
+def tile_bytes(ctx):
+    """Compulsory bytes per launch of each kernel: every input read once,
+    every output written once, each PSF node spectrum read once.
+
+    With N the frame and HP = (N/2) N complex64 = 4 N^2 bytes a packed
+    half-plane, per tile with K_x column masks:
+      col_H      : (K_x + 1) HP               (Z_kx in, Yc out)
+      row_resid  : 2 HP + 8 N^2               (Yc in, Rr out, (y, W) frame in)
+      col_Ht     : (1 + K_x) HP               (Rr in, G_kx out)
+      row_update : 2 K_x HP + 12 N^2          (G_kx in, Z_kx out, x and u in, x out)
+      consensus  : 12 bytes per (tile, support pixel): x, u in, u out
+    plus, for col_H and col_Ht, every PSF node spectrum once (HP each).
+    """
+    N = ctx.tiles[0].frame
+    HP = 4 * N * N
+    out = dict(col_H=0, row_resid=0, col_Ht=0, row_update=0, consensus=0)
+    for d in ctx.tiles:
+        kx = d.n_terms_x
+        out["col_H"] += (kx + 1) * HP
+        out["row_resid"] += 2 * HP + 8 * N * N
+        out["col_Ht"] += (1 + kx) * HP
+        out["row_update"] += 2 * kx * HP + 12 * N * N
+        out["consensus"] += 12 * d.support_h * d.support_w
+    nodes = ctx.params.G_y * ctx.params.G_x
+    out["col_H"] += nodes * HP
+    out["col_Ht"] += nodes * HP
+    return out
+
+
+def cpu_baseline(scene, psfs, y, W, w, budget_s=20.0):
+    """The FP64 oracle (direct convolution, single process) on a bounded
+    sample of the same workload: Local-Solver steps on seeded sampled tiles,
+    extrapolated to the whole image by tile count."""
+    from oracle import solver
+    from oracle.layout import make_layout
+    from oracle.solver import Problem
+
+    L = make_layout(w.M, w.tiles, w.pitch, w.overlap, w.psf_size, w.grid)
+    prob = Problem(L, psfs, y, W, lam=w.lam, reg_param=w.eps, gamma=w.gamma, rho=w.rho)
+    rng = np.random.default_rng(12345)
+    order = rng.permutation(L.n_tiles)
+    x0 = solver.initial_tiles(prob, "observed")
+    t_start = time.perf_counter()
+    el = 0.0
+    steps = 0
+    for t in order:
+        tau = solver.step_size(prob, t)          # setup, not timed
+        ts = time.perf_counter()
+        solver.local_solve(prob, t, x0[t], x0[t], 1, tau)
+        el += time.perf_counter() - ts
+        steps += 1
+        if time.perf_counter() - t_start > budget_s:
+            break
+    per_tile_step = el / steps
+    rate = (w.M * w.M) / (per_tile_step * L.n_tiles) / 1e6
+    return {"value": rate, "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"1 Local-Solver step (H + H^T + TV gradient + projected update) on each of "
+                      f"{steps} seeded-random tiles of {L.n_tiles} ({el:.1f} s, fp64 direct convolution, "
+                      f"one process); whole-image rate extrapolated by tile count"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (for HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this solver runs all tiles on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_direction": a.numel() * 4}))
+        return
+
+    print("# building workload", file=sys.stderr, flush=True)
+    ctx, w, scene, psfs, y, W = build_workload()
+    n_outer, n_inner = w.n_outer, w.n_inner
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ctx.init()
+        res = ctx.run(n_outer, n_inner)
+        ctx.assemble()
+        return res
+
+    print("# warmup", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    print("# timed", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    res = None
+    for _ in range(args.steps):
+        res = step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    ms_per_step = ms_total / args.steps
+    iters = n_outer * n_inner
+    value = (w.M * w.M) * iters * args.steps / (ms_total * 1e-3) / 1e6
+
+    # Per-kernel launch durations (HIP events on the context stream).
+    kms = ctx.time_kernels(reps=20)
+    kb = tile_bytes(ctx)
+    per_step_ms = {k: kms[k] * iters for k in KERNELS_PER_STEP}
+    dom = max(per_step_ms, key=per_step_ms.get)
+    achieved = kb[dom] / (kms[dom] * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", f"{dom}_batched_hbm_traffic.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            tj = json.load(fh)
+        if tj.get("kernel_source_hash") == kernel_source_hash():
+            traffic = tj.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dom, "kernel_ms": round(kms[dom], 5),
+                "algorithmic_bytes_per_launch": kb[dom],
+                "all_kernels_ms": {k: round(v, 5) for k, v in kms.items()},
+                "all_kernels_GBps": {k: round(kb[k] / (kms[k] * 1e-3) / 1e9, 1) for k in kms}}
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched: 2048x2048 image, 8x8 tiles (32-px overlap, uneven edge tiles), "
+                               "8x8 grid of 31x31 Moffat PSFs, Poisson+read noise, smoothed TV + positivity, "
+                               "200 iterations (20 D-R rounds x 10 Local-Solver steps), one solve per step",
+                   "global_pixels": w.M * w.M, "iterations": iters, "tiles": ctx.n_tiles,
+                   "fft_frame": ctx.tiles[0].frame, "parallelism": "single GPU, all tiles batched"},
+        "final_residual": res[-1] if res else None,
+        "wall_s": round(wall, 3),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(scene, psfs, y, W, w, args.cpu_budget)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -104,8 +104,9 @@ typedef struct deblur_tile_desc {
     int32_t block_h, block_w;
     int64_t x_offset;               /* float offset of the tile in support-packed arrays     */
     int64_t y_offset;               /* float offset of the tile in block-packed arrays       */
-    int32_t n_terms;                /* PSF terms K_t of the tile's operator                  */
+    int32_t n_terms;                /* PSF terms K_t = n_terms_y * n_terms_x of the operator  */
     int32_t frame;                  /* FFT frame size used for the tile                      */
+    int32_t n_terms_y, n_terms_x;   /* PSF nodes per axis whose weight touches the support  */
 } deblur_tile_desc;
 
 /* Create a context.  psfs_host: host [G_y][G_x][P][P] fp32, PSF of node

@@ -52,6 +52,7 @@ class TileDesc(ctypes.Structure):
         ("block_h", ctypes.c_int32), ("block_w", ctypes.c_int32),
         ("x_offset", ctypes.c_int64), ("y_offset", ctypes.c_int64),
         ("n_terms", ctypes.c_int32), ("frame", ctypes.c_int32),
+        ("n_terms_y", ctypes.c_int32), ("n_terms_x", ctypes.c_int32),
     ]
 
 

@@ -391,6 +391,8 @@ int build_layout(deblur_ctx* c, const float* psfs_host) {
             d.y_offset = yo;
             d.n_terms = ti.nky * ti.nkx;
             d.frame = N;
+            d.n_terms_y = ti.nky;
+            d.n_terms_x = ti.nkx;
             xo += (int64_t)ti.sy * ti.sx;
             yo += (int64_t)ti.by * ti.bx;
             double om = 0.0;

@@ -134,11 +134,20 @@ __device__ __forceinline__ void slot_pos(int lane, int s, int& line, int& elem) 
 // p = 0) and receives the output in layout L_{radix of the last pass}.  sw is
 // the wave's LDS region (1280/n lines of stride line_stride<n>()), tw a
 // twiddle table with tw[TS * e] = exp(-2 pi i e / n).
+// Opaque copy of the lane index: address arithmetic derived from it is redone
+// where it is used instead of being hoisted (and kept live) across passes and
+// across the callers' loops, which would cost one VGPR per slot and pass.
+__device__ __forceinline__ int fresh_lane(int lane) {
+    asm volatile("" : "+v"(lane));
+    return lane;
+}
+
 template <int n, int DIR, int TS, int p = 0, int Ns = 1>
 __device__ __forceinline__ void fft_passes(float2 (&v)[kV], float2* __restrict__ sw,
-                                           const float2* __restrict__ tw, int lane) {
+                                           const float2* __restrict__ tw, int lane_in) {
     constexpr int np = Plan<n>::np;
     if constexpr (p < np) {
+        const int lane = fresh_lane(lane_in);
         constexpr int R = pass_radix<n, DIR, p>();
         constexpr int NB = kV / R;
         constexpr int nR = n / R;
@@ -180,7 +189,7 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[kV], float2* __restrict__
             }
             wave_sync();
         }
-        fft_passes<n, DIR, TS, p + 1, Ns * R>(v, sw, tw, lane);
+        fft_passes<n, DIR, TS, p + 1, Ns * R>(v, sw, tw, lane_in);
     }
 }
 

@@ -250,13 +250,61 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_inv(const float2* __restrict
 // Column kernels
 // ---------------------------------------------------------------------------
 
+// Loads the spectrum values of one term for the wave's columns, in the
+// forward transform's output layout (prefetched one term ahead).
+template <int N>
+__device__ __forceinline__ void load_spec(float2 (&sp)[kV], const float2* __restrict__ base, int f0, int lane) {
+    constexpr int RL = last_radix<N, kFwd>();
+#pragma unroll
+    for (int s = 0; s < kV; ++s) {
+        int q, g;
+        slot_pos<N, RL>(lane, s, q, g);
+        sp[s] = base[(size_t)(f0 + q) * N + g];
+    }
+}
+
+// acc += spec . v for the wave's columns; column f = 0 holds the packed
+// DC/Nyquist pair: acc += c1 v + c2 conj(v(-g)) (c1 prefetched in sp,
+// c2 read from the spectrum's column N/2, v(-g) through col0).
+template <int N, bool CONJ>
+__device__ __forceinline__ void spec_mac(float2 (&acc)[kV], const float2 (&v)[kV], const float2 (&sp)[kV],
+                                         const float2* __restrict__ base, float2* __restrict__ col0, int f0,
+                                         int lane) {
+    constexpr int RL = last_radix<N, kFwd>();
+    if (f0 == 0) {   // wave-uniform: this wave owns column 0 as its line 0
+#pragma unroll
+        for (int s = 0; s < kV; ++s) {
+            int q, g;
+            slot_pos<N, RL>(lane, s, q, g);
+            if (q == 0) col0[g] = v[s];
+        }
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < kV; ++s) {
+            int q, g;
+            slot_pos<N, RL>(lane, s, q, g);
+            if (q == 0) {
+                const float2 vm = cconj(col0[(N - g) % N]);
+                const float2 c2 = base[(size_t)(N / 2) * N + g];
+                if (CONJ) acc[s] = cadd(acc[s], cadd(cmulc(v[s], sp[s]), cmulc(vm, c2)));
+                else acc[s] = cadd(acc[s], cadd(cmul(sp[s], v[s]), cmul(c2, vm)));
+            } else {
+                acc[s] = cadd(acc[s], CONJ ? cmulc(v[s], sp[s]) : cmul(sp[s], v[s]));
+            }
+        }
+        wave_sync();
+    } else {
+#pragma unroll
+        for (int s = 0; s < kV; ++s) acc[s] = cadd(acc[s], CONJ ? cmulc(v[s], sp[s]) : cmul(sp[s], v[s]));
+    }
+}
+
 // H: Yc[f][:] = IFFT_col( sum_{ky,kx} spec_k . FFT_col(a_ky . Z_kx[f][:]) )
 template <int N>
 __global__ __launch_bounds__(Cfg<N>::NT) void k_col_H(const float2* __restrict__ Zk, const TileInfo* __restrict__ tiles,
                                                       const float* __restrict__ tentY, const float2* __restrict__ spec,
                                                       const float2* __restrict__ twg, float2* __restrict__ Yc) {
     using C = Cfg<N>;
-    constexpr int RL = last_radix<N, kFwd>();
     __shared__ float2 lds[C::W * C::LwC * C::LSC];
     __shared__ float2 tw[N];
     __shared__ float2 col0[N];
@@ -264,60 +312,36 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_H(const float2* __restrict__
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int f0 = blockIdx.x * C::CB + wave * C::LwC;
     load_twiddles<N>(tw, twg, tid);
-    __syncthreads();
-    const TileInfo ti = tiles[t];
+    const TileInfo* tp = tiles + t;
+    const int nky = tp->nky, nkx = tp->nkx, ty = tp->ty;
+    const int nterm = nky * nkx;
     float2* sw = lds + wave * C::LwC * C::LSC;
-    float2 acc[kV];
+    float2 acc[kV], sp[kV];
 #pragma unroll
     for (int s = 0; s < kV; ++s) acc[s] = make_float2(0.f, 0.f);
-    for (int kx = 0; kx < ti.nkx; ++kx) {
+    // terms kx-major; Z_kx is re-read for every ky (it stays in L2)
+    load_spec<N>(sp, spec + (size_t)tp->spec[0] * C::NSPEC, f0, lane);
+    __syncthreads();
+    for (int term = 0; term < nterm; ++term) {
+        const int kx = term / nky, ky = term - kx * nky;
         const float2* zt = Zk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)f0 * N;
-        float2 zin[kV];
-#pragma unroll
-        for (int s = 0; s < kV; ++s) {
-            int q, g;
-            slot_pos<N, 5>(lane, s, q, g);
-            zin[s] = zt[(size_t)q * N + g];
-        }
-        for (int ky = 0; ky < ti.nky; ++ky) {
-            const float* am = tentY + ((size_t)ti.ty * kMaxK + ky) * N;
-            float2 v[kV];
+        const float* am = tentY + ((size_t)ty * kMaxK + ky) * N;
+        float2 v[kV];
+        {
+            const int ln = fresh_lane(lane);
 #pragma unroll
             for (int s = 0; s < kV; ++s) {
                 int q, g;
-                slot_pos<N, 5>(lane, s, q, g);
-                v[s] = cscale(zin[s], am[g]);
+                slot_pos<N, 5>(ln, s, q, g);
+                v[s] = cscale(zt[(size_t)q * N + g], am[g]);
             }
-            fft_passes<N, kFwd, 1>(v, sw, tw, lane);
-            const float2* sp = spec + (size_t)tiles[t].spec[ky * kMaxK + kx] * C::NSPEC;
-            if (f0 == 0) {
-#pragma unroll
-                for (int s = 0; s < kV; ++s) {
-                    int q, g;
-                    slot_pos<N, RL>(lane, s, q, g);
-                    if (q == 0) col0[g] = v[s];
-                }
-                wave_sync();
-#pragma unroll
-                for (int s = 0; s < kV; ++s) {
-                    int q, g;
-                    slot_pos<N, RL>(lane, s, q, g);
-                    if (q == 0) {
-                        const float2 vm = col0[(N - g) % N];
-                        acc[s] = cadd(acc[s], cadd(cmul(sp[g], v[s]), cmul(sp[(size_t)(N / 2) * N + g], cconj(vm))));
-                    } else {
-                        acc[s] = cadd(acc[s], cmul(sp[(size_t)q * N + g], v[s]));
-                    }
-                }
-                wave_sync();
-            } else {
-#pragma unroll
-                for (int s = 0; s < kV; ++s) {
-                    int q, g;
-                    slot_pos<N, RL>(lane, s, q, g);
-                    acc[s] = cadd(acc[s], cmul(sp[(size_t)(f0 + q) * N + g], v[s]));
-                }
-            }
+        }
+        fft_passes<N, kFwd, 1>(v, sw, tw, lane);
+        const float2* base = spec + (size_t)tp->spec[ky * kMaxK + kx] * C::NSPEC;
+        spec_mac<N, false>(acc, v, sp, base, col0, f0, lane);
+        if (term + 1 < nterm) {
+            const int kx2 = (term + 1) / nky, ky2 = term + 1 - kx2 * nky;
+            load_spec<N>(sp, spec + (size_t)tp->spec[ky2 * kMaxK + kx2] * C::NSPEC, f0, lane);
         }
     }
     fft_passes<N, kInv, 1>(acc, sw, tw, lane);
@@ -332,11 +356,10 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_H(const float2* __restrict__
 
 // H^T: Gk[kx][f][:] = sum_ky a_ky . IFFT_col( conj(spec_k) . FFT_col(Rr[f][:]) )
 template <int N>
-__global__ __launch_bounds__(Cfg<N>::NT) void k_col_Ht(const float2* __restrict__ Rr, const TileInfo* __restrict__ tiles,
+__global__ __launch_bounds__(Cfg<N>::NT, 2) void k_col_Ht(const float2* __restrict__ Rr, const TileInfo* __restrict__ tiles,
                                                        const float* __restrict__ tentY, const float2* __restrict__ spec,
                                                        const float2* __restrict__ twg, float2* __restrict__ Gk) {
     using C = Cfg<N>;
-    constexpr int RL = last_radix<N, kFwd>();
     __shared__ float2 lds[C::W * C::LwC * C::LSC];
     __shared__ float2 tw[N];
     __shared__ float2 col0[N];
@@ -344,10 +367,11 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_Ht(const float2* __restrict_
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int f0 = blockIdx.x * C::CB + wave * C::LwC;
     load_twiddles<N>(tw, twg, tid);
-    __syncthreads();
-    const TileInfo ti = tiles[t];
+    const TileInfo* tp = tiles + t;
+    const int nky = tp->nky, nkx = tp->nkx, ty = tp->ty;
+    const int nterm = nky * nkx;
     float2* sw = lds + wave * C::LwC * C::LSC;
-    float2 S[kV];
+    float2 S[kV], sp[kV], acc[kV];
     {
         const float2* rt = Rr + (size_t)t * C::SPEC + (size_t)f0 * N;
 #pragma unroll
@@ -357,49 +381,40 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_Ht(const float2* __restrict_
             S[s] = rt[(size_t)q * N + g];
         }
     }
+    load_spec<N>(sp, spec + (size_t)tp->spec[0] * C::NSPEC, f0, lane);
+    __syncthreads();
     fft_passes<N, kFwd, 1>(S, sw, tw, lane);
-    if (f0 == 0) {
+    for (int term = 0; term < nterm; ++term) {
+        const int kx = term / nky, ky = term - kx * nky;
+        if (ky == 0) {
 #pragma unroll
-        for (int s = 0; s < kV; ++s) {
-            int q, g;
-            slot_pos<N, RL>(lane, s, q, g);
-            if (q == 0) col0[g] = S[s];
+            for (int s = 0; s < kV; ++s) acc[s] = make_float2(0.f, 0.f);
         }
-        wave_sync();
-    }
-    for (int kx = 0; kx < ti.nkx; ++kx) {
-        float2 acc[kV];
+        const float2* base = spec + (size_t)tp->spec[ky * kMaxK + kx] * C::NSPEC;
+        float2 v[kV];
 #pragma unroll
-        for (int s = 0; s < kV; ++s) acc[s] = make_float2(0.f, 0.f);
-        for (int ky = 0; ky < ti.nky; ++ky) {
-            const float2* sp = spec + (size_t)tiles[t].spec[ky * kMaxK + kx] * C::NSPEC;
-            float2 v[kV];
-#pragma unroll
-            for (int s = 0; s < kV; ++s) {
-                int q, g;
-                slot_pos<N, RL>(lane, s, q, g);
-                if (f0 == 0 && q == 0) {
-                    const float2 Sm = col0[(N - g) % N];
-                    v[s] = cadd(cmulc(S[s], sp[g]), cmulc(cconj(Sm), sp[(size_t)(N / 2) * N + g]));
-                } else {
-                    v[s] = cmulc(S[s], sp[(size_t)(f0 + q) * N + g]);
-                }
-            }
-            fft_passes<N, kInv, 1>(v, sw, tw, lane);
-            const float* am = tentY + ((size_t)ti.ty * kMaxK + ky) * N;
-#pragma unroll
-            for (int s = 0; s < kV; ++s) {
-                int q, g;
-                slot_pos<N, 5>(lane, s, q, g);
-                acc[s] = cadd(acc[s], cscale(v[s], am[g]));
-            }
+        for (int s = 0; s < kV; ++s) v[s] = make_float2(0.f, 0.f);
+        spec_mac<N, true>(v, S, sp, base, col0, f0, lane);
+        if (term + 1 < nterm) {
+            const int kx2 = (term + 1) / nky, ky2 = term + 1 - kx2 * nky;
+            load_spec<N>(sp, spec + (size_t)tp->spec[ky2 * kMaxK + kx2] * C::NSPEC, f0, lane);
         }
-        float2* gt = Gk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)f0 * N;
+        fft_passes<N, kInv, 1>(v, sw, tw, lane);
+        const float* am = tentY + ((size_t)ty * kMaxK + ky) * N;
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
             int q, g;
             slot_pos<N, 5>(lane, s, q, g);
-            gt[(size_t)q * N + g] = acc[s];
+            acc[s] = cadd(acc[s], cscale(v[s], am[g]));
+        }
+        if (ky == nky - 1) {
+            float2* gt = Gk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)f0 * N;
+#pragma unroll
+            for (int s = 0; s < kV; ++s) {
+                int q, g;
+                slot_pos<N, 5>(lane, s, q, g);
+                gt[(size_t)q * N + g] = acc[s];
+            }
         }
     }
 }
@@ -510,46 +525,31 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_resid(const float2* __restri
     if (tid == 0) obj_part[t * C::RG + blockIdx.x] = 0.5f * tot;
 }
 
-// Gradient of the regulariser at support pixel (i, c) of frame xt.
-__device__ __forceinline__ float reg_grad(const float* __restrict__ xt, int N, int i, int c, int sy, int sx,
-                                          const SolveParams& P) {
-    const bool circ = P.bc != 0;
-    auto X = [&](int a, int b) { return xt[(size_t)a * N + b]; };
-    auto q = [&](int a, int b, float& qh, float& qv) {
-        const float x0 = X(a, b);
-        float gh, gv;
-        if (circ) {
-            gh = X(a, b + 1 < sx ? b + 1 : 0) - x0;
-            gv = X(a + 1 < sy ? a + 1 : 0, b) - x0;
-        } else {
-            gh = (b + 1 < sx) ? X(a, b + 1) - x0 : 0.f;
-            gv = (a + 1 < sy) ? X(a + 1, b) - x0 : 0.f;
-        }
-        const float n2 = gh * gh + gv * gv;
-        float sc;
-        if (P.reg == 0) sc = 1.0f / sqrtf(n2 + P.reg_param * P.reg_param);
-        else sc = P.reg_param / fmaxf(sqrtf(n2), P.reg_param);
-        qh = sc * gh;
-        qv = sc * gv;
-    };
-    float qh, qv, g;
-    q(i, c, qh, qv);
-    g = -qh - qv;
-    if (c >= 1 || circ) {
-        float a, b;
-        q(i, c >= 1 ? c - 1 : sx - 1, a, b);
-        g += a;
-    }
-    if (i >= 1 || circ) {
-        float a, b;
-        q(i >= 1 ? i - 1 : sy - 1, c, a, b);
-        g += b;
-    }
-    return g;
+// Scale of the regulariser's derivative for a forward-difference vector g:
+// d phi / d g = s(g) g with s = 1/sqrt(|g|^2 + eps^2) (smoothed TV) or
+// delta / max(|g|, delta) (Huber).
+__device__ __forceinline__ float reg_scale(float gh, float gv, const SolveParams& P) {
+    const float n2 = gh * gh + gv * gv;
+    if (P.reg == 0) return rsqrtf(n2 + P.reg_param * P.reg_param);
+    return P.reg_param * __frcp_rn(fmaxf(sqrtf(n2), P.reg_param));
 }
+
+// Tasks of the column-strip update phase: every column split into segments
+// of kSeg rows, (N / RB-row workgroup) -> N * RB / kSeg tasks, a multiple of NT.
+constexpr int kSeg = 8;
 
 // H^T r (from Gk), regulariser and metric terms, projected step; then the
 // masked row spectra of the new iterate for the next step.
+//
+// Phase 1: per mask k, transposed load of G_k, row C2R, accumulate b_k . (.)
+//          into the data gradient (registers), then park it in LDS as
+//          natural [row][col] floats.
+// Phase 2: one thread per (column, 8-row segment): walks down the rows
+//          carrying x at columns c-1, c, c+1 and the vertical term of the
+//          row above, so each pixel loads one new row triple and evaluates
+//          two regulariser scales; writes the new x to HBM and to LDS.
+// Phase 3: each wave reads its rows of the new x from LDS and, per mask k,
+//          does the forward row FFT and the transposed store of Z_k.
 template <int N>
 __global__ __launch_bounds__(Cfg<N>::NT) void k_row_update(
         const float2* __restrict__ Gk, const float* __restrict__ xc, const float* __restrict__ u,
@@ -558,60 +558,130 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_update(
         const float2* __restrict__ twg, float* __restrict__ xn, float2* __restrict__ Zk) {
     using C = Cfg<N>;
     constexpr int n = C::n;
+    static_assert(C::RB * N * sizeof(float) <= C::RB * C::LSR * sizeof(float2), "LDS view too small");
+    static_assert((N * (C::RB / kSeg)) % C::NT == 0, "update tasks do not divide the workgroup");
     __shared__ float2 sbuf[C::RB * C::LSR];
     __shared__ float2 tw[N];
+    float* sg = reinterpret_cast<float*>(sbuf);   // [RB][N] natural view
     const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_twiddles<N>(tw, twg, tid);
     const TileInfo ti = tiles[t];
     float2* sw = sbuf + wave * C::LwR * C::LSR;
-    float2 gd[kV];
+
+    // ---- phase 1: data gradient H^T r
+    {
+        float2 gd[kV];
 #pragma unroll
-    for (int s = 0; s < kV; ++s) gd[s] = make_float2(0.f, 0.f);
-    for (int kx = 0; kx < ti.nkx; ++kx) {
+        for (int s = 0; s < kV; ++s) gd[s] = make_float2(0.f, 0.f);
+        for (int kx = 0; kx < ti.nkx; ++kx) {
+            __syncthreads();
+            load_spectrum_T<N>(sbuf, Gk + ((size_t)t * kMaxK + kx) * C::SPEC, i0, tid);
+            __syncthreads();
+            float2 v[kV];
+            row_c2r_wave<N>(v, sw, tw, lane);
+            const float* bm = tentX + ((size_t)ti.tx * kMaxK + kx) * N;
+#pragma unroll
+            for (int s = 0; s < kV; ++s) {
+                int q, m;
+                slot_pos<n, 5>(lane, s, q, m);
+                const float2 b = *reinterpret_cast<const float2*>(bm + 2 * m);
+                gd[s].x += b.x * v[s].x;
+                gd[s].y += b.y * v[s].y;
+            }
+        }
         __syncthreads();
-        load_spectrum_T<N>(sbuf, Gk + ((size_t)t * kMaxK + kx) * C::SPEC, i0, tid);
-        __syncthreads();
-        float2 v[kV];
-        row_c2r_wave<N>(v, sw, tw, lane);
-        const float* bm = tentX + ((size_t)ti.tx * kMaxK + kx) * N;
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
             int q, m;
             slot_pos<n, 5>(lane, s, q, m);
-            gd[s].x += bm[2 * m] * v[s].x;
-            gd[s].y += bm[2 * m + 1] * v[s].y;
+            *reinterpret_cast<float2*>(sg + (wave * C::LwR + q) * N + 2 * m) = gd[s];
         }
+        __syncthreads();
     }
-    const float* xt = xc + (size_t)t * N * N;
-    const float* ut = u + (size_t)t * N * N;
-    float* xo = xn + (size_t)t * N * N;
-    const float tt = tau[t];
-    const float* oy = omY + (size_t)ti.ty * N;
-    const float* ox = omX + (size_t)ti.tx * N;
+
+    // ---- phase 2: regulariser, metric term, projected step (column strips)
+    {
+        const float* xt = xc + (size_t)t * N * N;
+        const float* ut = u + (size_t)t * N * N;
+        float* xo = xn + (size_t)t * N * N;
+        const float tt = tau[t];
+        const float* oy = omY + (size_t)ti.ty * N;
+        const float* ox = omX + (size_t)ti.tx * N;
+        const int sy = ti.sy, sx = ti.sx;
+        const bool circ = P.bc != 0;
+        constexpr int SEGS = C::RB / kSeg;
+        for (int task = tid; task < N * SEGS; task += C::NT) {
+            const int c = task % N;
+            const int ia = i0 + (task / N) * kSeg;
+            const bool colin = c < sx;
+            // neighbour columns (wrapped for the circular difference; -1: none)
+            const int cl = c >= 1 ? c - 1 : (circ ? sx - 1 : -1);
+            const int cr = c + 1 < sx ? c + 1 : (circ ? 0 : -1);
+            // rows ia-1 .. ia+kSeg of x at columns (cl, c, cr), all loads in flight at once
+            float X[kSeg + 2][3];
+            float U[kSeg];
+#pragma unroll
+            for (int j = 0; j < kSeg + 2; ++j) {
+                int rr = ia - 1 + j;
+                if (rr < 0) rr = circ ? sy - 1 : -1;
+                else if (rr >= sy) rr = (circ && rr == sy) ? 0 : -1;
+                const bool ok = colin && rr >= 0;
+                const float* rowp = xt + (size_t)(ok ? rr : 0) * N;
+                X[j][0] = (ok && cl >= 0) ? rowp[cl] : 0.f;
+                X[j][1] = ok ? rowp[c] : 0.f;
+                X[j][2] = (ok && cr >= 0) ? rowp[cr] : 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < kSeg; ++k) {
+                const int i = ia + k;
+                U[k] = (colin && i < sy) ? ut[(size_t)i * N + c] : 0.f;
+            }
+            const float oxc = colin ? ox[c] : 0.f;
+            // vertical term of the row above the segment: qv(ia-1, c)
+            float qv_up = 0.f;
+            if (colin && (ia >= 1 || circ) && ia < sy) {
+                const float gh = cr >= 0 ? X[0][2] - X[0][1] : 0.f;
+                const float gv = X[1][1] - X[0][1];
+                qv_up = reg_scale(gh, gv, P) * gv;
+            }
+#pragma unroll
+            for (int k = 0; k < kSeg; ++k) {
+                const int i = ia + k;
+                float val = 0.f;
+                if (colin && i < sy) {
+                    const bool nxt = (i + 1 < sy) || circ;
+                    const float xm = X[k + 1][1];
+                    const float gh = cr >= 0 ? X[k + 1][2] - xm : 0.f;
+                    const float gv = nxt ? X[k + 2][1] - xm : 0.f;
+                    const float sc = reg_scale(gh, gv, P);
+                    float g = qv_up - sc * (gh + gv);
+                    if (cl >= 0) {
+                        const float xl = X[k + 1][0];
+                        const float ghl = xm - xl;   // column c is the right neighbour of c-1
+                        const float gvl = nxt ? X[k + 2][0] - xl : 0.f;
+                        g += reg_scale(ghl, gvl, P) * ghl;
+                    }
+                    qv_up = sc * gv;
+                    const float alpha = P.gamma * oy[i] * oxc;
+                    const float grad = sg[(i - i0) * N + c] + P.lambda * g + alpha * (xm - U[k]);
+                    val = xm - tt * grad;
+                    if (P.positivity) val = fmaxf(val, 0.f);
+                }
+                xo[(size_t)i * N + c] = val;
+                sg[(i - i0) * N + c] = val;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- phase 3: forward row spectra of b_k . x_new
     float2 xv[kV];
 #pragma unroll
     for (int s = 0; s < kV; ++s) {
         int q, m;
         slot_pos<n, 5>(lane, s, q, m);
-        const int i = i0 + wave * C::LwR + q;
-        float out[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int c = 2 * m + h;
-            float val = 0.f;
-            if (i < ti.sy && c < ti.sx) {
-                const float x0 = xt[(size_t)i * N + c];
-                const float alpha = P.gamma * oy[i] * ox[c];
-                const float g = (h ? gd[s].y : gd[s].x) + P.lambda * reg_grad(xt, N, i, c, ti.sy, ti.sx, P) +
-                                alpha * (x0 - ut[(size_t)i * N + c]);
-                val = x0 - tt * g;
-                if (P.positivity) val = fmaxf(val, 0.f);
-            }
-            out[h] = val;
-        }
-        xv[s] = make_float2(out[0], out[1]);
-        *reinterpret_cast<float2*>(xo + (size_t)i * N + 2 * m) = xv[s];
+        xv[s] = *reinterpret_cast<const float2*>(sg + (wave * C::LwR + q) * N + 2 * m);
     }
     for (int kx = 0; kx < ti.nkx; ++kx) {
         const float* bm = tentX + ((size_t)ti.tx * kMaxK + kx) * N;
@@ -620,7 +690,8 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_update(
         for (int s = 0; s < kV; ++s) {
             int q, m;
             slot_pos<n, 5>(lane, s, q, m);
-            v[s] = make_float2(bm[2 * m] * xv[s].x, bm[2 * m + 1] * xv[s].y);
+            const float2 b = *reinterpret_cast<const float2*>(bm + 2 * m);
+            v[s] = make_float2(b.x * xv[s].x, b.y * xv[s].y);
         }
         __syncthreads();
         row_fft_wave<N>(v, sw, tw, lane);
