@@ -211,6 +211,66 @@ int deblur_time_kernels(deblur_ctx* ctx, int32_t reps, float* ms_host);
  *              in [batch][n/2][n] complex -> out [batch][n][n] real. */
 int deblur_debug_fft(int32_t n, int32_t batch, int32_t which, const float* in, float* out, void* stream);
 
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start.  A 4-layer 3x3 convolutional network (1 -> 32 -> 32 ->
+ * 32 -> 1 channels, ReLU, residual output, 19,105 parameters) predicts a
+ * tile's solution from its normalised blurred input; it only sets the
+ * starting point x^0 = u^0 of Algorithm 1, which then runs unchanged.
+ * Weights and activations are BF16 with FP32 accumulation (MFMA for the
+ * 32 -> 32 layers); the master weights and the Adam state are FP32.
+ * Parameter vector layout: per layer W[C_out][C_in][3][3] then b[C_out].
+ * Images are device [B][H][W] fp32, row-major; H a multiple of 8, W of 32.
+ * ------------------------------------------------------------------------- */
+typedef struct deblur_cnn deblur_cnn;
+
+/* Create a network with buffers for up to max_batch images of
+ * max_h x max_w.  params_host: 19,105 floats, or NULL for a seeded He
+ * initialisation (last layer scaled by 0.1).  stream as for deblur_create. */
+int deblur_cnn_create(const float* params_host, int32_t seed, int32_t max_batch, int32_t max_h, int32_t max_w,
+                      void* stream, deblur_cnn** out);
+void deblur_cnn_destroy(deblur_cnn* net);
+const char* deblur_cnn_last_error(const deblur_cnn* net);
+int deblur_cnn_get_params(deblur_cnn* net, float* params_host);
+/* Replaces the weights and resets the optimiser state. */
+int deblur_cnn_set_params(deblur_cnn* net, const float* params_host);
+
+/* out = img + conv4(relu(conv3(relu(conv2(relu(conv1(img))))))) with zero
+ * padding outside each image's valid region (valid_host: host [B][2] rows,
+ * columns, or NULL for the whole image); out is 0 outside it. */
+int deblur_cnn_forward(deblur_cnn* net, const float* img, const int32_t* valid_host, int32_t B, int32_t H,
+                       int32_t W, float* out);
+
+/* Loss mean((out - target)^2) over all pixels and its gradient w.r.t. the
+ * parameters (grad_host: 19,105 floats, may be NULL; loss_host may be NULL). */
+int deblur_cnn_loss_grad(deblur_cnn* net, const float* img, const float* target, int32_t B, int32_t H, int32_t W,
+                         double* loss_host, float* grad_host);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that loss. */
+int deblur_cnn_train_step(deblur_cnn* net, const float* img, const float* target, int32_t B, int32_t H, int32_t W,
+                          float lr, double* loss_host);
+
+/* Mean milliseconds of a whole forward pass and of one 32 -> 32 MFMA layer
+ * over reps launches (HIP events on the network stream): ms_host[2]. */
+int deblur_cnn_time_forward(deblur_cnn* net, const float* img, int32_t B, int32_t H, int32_t W, int32_t reps,
+                            float* ms_host);
+
+/* The network input of every tile as the warm start computes it: device
+ * frames [n_tiles][frame][frame] = y (nearest observed pixel) / s_t on the
+ * support, 0 elsewhere, with s_t = mean over the block of max(y, 0) (floored
+ * at 1e-6) written to scale_host (host float[n_tiles], may be NULL). */
+int deblur_warm_inputs(deblur_ctx* ctx, float* frames, float* scale_host);
+
+/* Warm start of every tile: input y (nearest observed pixel) / s_t on the
+ * support, s_t = mean over the block of max(y, 0); x^0 = max(0, s_t * net).
+ * Per tile the network's start is kept only if its projected-gradient map
+ * ||x0 - max(0, x0 - tau_t grad f_t(x0))|| is at least 0.1% smaller than that
+ * of the plain start (DEBLUR_INIT_OBSERVED); otherwise the tile falls back to
+ * the plain start, so the network never starts a tile worse by that measure.  use_cnn_host (may be NULL): host int32[n_tiles], 1 where
+ * the network's start was kept; *n_fallback: tiles that fell back.  The
+ * network must share the context's stream and have max_h, max_w >= frame. */
+int deblur_init_cnn(deblur_ctx* ctx, deblur_cnn* net, int32_t* use_cnn_host, int32_t* n_fallback);
+
 #ifdef __cplusplus
 }
 #endif

@@ -89,6 +89,17 @@ def lib():
         "deblur_blur_global": ([vp, f32p, f32p], i32),
         "deblur_time_kernels": ([vp, i32, ctypes.POINTER(ctypes.c_float)], i32),
         "deblur_debug_fft": ([i32, i32, i32, f32p, f32p, vp], i32),
+        "deblur_cnn_create": ([vp, i32, i32, i32, i32, vp, ctypes.POINTER(vp)], i32),
+        "deblur_cnn_destroy": ([vp], None),
+        "deblur_cnn_last_error": ([vp], ctypes.c_char_p),
+        "deblur_cnn_get_params": ([vp, vp], i32),
+        "deblur_cnn_set_params": ([vp, vp], i32),
+        "deblur_cnn_forward": ([vp, f32p, vp, i32, i32, i32, f32p], i32),
+        "deblur_cnn_loss_grad": ([vp, f32p, f32p, i32, i32, i32, dp, vp], i32),
+        "deblur_cnn_train_step": ([vp, f32p, f32p, i32, i32, i32, ctypes.c_float, dp], i32),
+        "deblur_cnn_time_forward": ([vp, f32p, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_float)], i32),
+        "deblur_init_cnn": ([vp, vp, vp, ctypes.POINTER(i32)], i32),
+        "deblur_warm_inputs": ([vp, f32p, ctypes.POINTER(ctypes.c_float)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -106,6 +117,9 @@ def exported_symbols():
         "deblur_solve_tiles", "deblur_consensus", "deblur_run", "deblur_get_state",
         "deblur_set_state", "deblur_assemble", "deblur_objective", "deblur_step_sizes",
         "deblur_blur_global", "deblur_time_kernels", "deblur_debug_fft",
+        "deblur_cnn_create", "deblur_cnn_destroy", "deblur_cnn_last_error", "deblur_cnn_get_params",
+        "deblur_cnn_set_params", "deblur_cnn_forward", "deblur_cnn_loss_grad", "deblur_cnn_train_step",
+        "deblur_cnn_time_forward", "deblur_init_cnn", "deblur_warm_inputs",
     ]
 
 
@@ -254,6 +268,23 @@ class Context:
         self._check(self._L.deblur_time_kernels(self._h, reps, out))
         return dict(zip(KERNEL_NAMES, out[:]))
 
+    def init_cnn(self, net):
+        """Warm start from the network with per-tile fallback; returns the
+        host array of per-tile flags (1: network start kept) and the number
+        of tiles that fell back."""
+        use = (ctypes.c_int32 * self.n_tiles)()
+        nf = ctypes.c_int32()
+        self._check(self._L.deblur_init_cnn(self._h, net._h, use, ctypes.byref(nf)))
+        return np.array(use[:], dtype=np.int32), nf.value
+
+    def warm_inputs(self):
+        """Network inputs [n_tiles, N, N] (device) and per-tile scales (host)."""
+        N = self.tiles[0].frame
+        frames = self._torch.empty((self.n_tiles, N, N), dtype=self._torch.float32, device="cuda")
+        sc = (ctypes.c_float * self.n_tiles)()
+        self._check(self._L.deblur_warm_inputs(self._h, _ptr(frames), sc))
+        return frames, np.array(sc[:], dtype=np.float64)
+
     # -- host-side layout helpers (no method arithmetic) ------------------------
     def pack_support(self, x_global):
         """Support-packed float32 host array from a host image on X."""
@@ -296,3 +327,81 @@ def debug_fft(n, which, data, stream=None):
     if rc != 0:
         raise DeblurError(rc, L.deblur_last_error(None).decode())
     return out
+
+
+N_CNN_PARAMS = 19105
+
+
+class Net:
+    """The warm-start network on the GPU (weights, Adam state, buffers)."""
+
+    def __init__(self, max_batch, max_h, max_w, params=None, seed=0, stream=None):
+        import torch
+        self._torch = torch
+        self._L = lib()
+        h = ctypes.c_void_p()
+        p = None
+        if params is not None:
+            p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+            if p.size != N_CNN_PARAMS:
+                raise ValueError("expected 19105 parameters")
+        rc = self._L.deblur_cnn_create(p.ctypes.data_as(ctypes.c_void_p) if p is not None else None, seed,
+                                       max_batch, max_h, max_w, _stream_handle(stream), ctypes.byref(h))
+        if rc != 0:
+            raise DeblurError(rc, self._L.deblur_cnn_last_error(None).decode())
+        self._h = h
+        self.max_batch, self.max_h, self.max_w = max_batch, max_h, max_w
+
+    def _check(self, rc):
+        if rc != 0:
+            raise DeblurError(rc, self._L.deblur_cnn_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.deblur_cnn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.empty(N_CNN_PARAMS, dtype=np.float32)
+        self._check(self._L.deblur_cnn_get_params(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        self._check(self._L.deblur_cnn_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p)))
+
+    def forward(self, img, valid=None):
+        B, H, W = img.shape
+        out = self._torch.empty_like(img)
+        v = None
+        if valid is not None:
+            v = np.ascontiguousarray(np.asarray(valid, dtype=np.int32))
+        self._check(self._L.deblur_cnn_forward(self._h, _ptr(img), v.ctypes.data_as(ctypes.c_void_p) if v is not None
+                                               else None, B, H, W, _ptr(out)))
+        return out
+
+    def loss_grad(self, img, target):
+        B, H, W = img.shape
+        loss = ctypes.c_double()
+        g = np.empty(N_CNN_PARAMS, dtype=np.float32)
+        self._check(self._L.deblur_cnn_loss_grad(self._h, _ptr(img), _ptr(target), B, H, W, ctypes.byref(loss),
+                                                 g.ctypes.data_as(ctypes.c_void_p)))
+        return loss.value, g
+
+    def train_step(self, img, target, lr):
+        B, H, W = img.shape
+        loss = ctypes.c_double()
+        self._check(self._L.deblur_cnn_train_step(self._h, _ptr(img), _ptr(target), B, H, W, lr, ctypes.byref(loss)))
+        return loss.value
+
+    def time_forward(self, img, reps=10):
+        B, H, W = img.shape
+        ms = (ctypes.c_float * 2)()
+        self._check(self._L.deblur_cnn_time_forward(self._h, _ptr(img), B, H, W, reps, ms))
+        return ms[0], ms[1]

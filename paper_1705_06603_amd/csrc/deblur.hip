@@ -13,6 +13,7 @@
 
 #include "../../include/deblur.h"
 #include "kernels.h"
+#include "cnn.h"
 
 using dbl::Cover;
 using dbl::PackDesc;
@@ -144,6 +145,12 @@ struct deblur_ctx {
     double* h_pinned = nullptr;
     bool have_obs = false;
     bool have_state = false;
+    // warm-start bookkeeping
+    float* tile_scale = nullptr;
+    int* sdim = nullptr;
+    int* bdim = nullptr;
+    double* gmap = nullptr;
+    int* use_cnn = nullptr;
     std::vector<void*> allocs;
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_defs;
@@ -493,6 +500,17 @@ int upload_tables(deblur_ctx* c, const float* psfs_host) {
     if ((rc = dev_alloc(c, &c->sorg, so.size()))) return rc;
     if ((rc = dev_alloc(c, &c->borg, bo.size()))) return rc;
     if ((rc = dev_alloc(c, &c->xorg, xo.size()))) return rc;
+    std::vector<int> sd(2 * c->nt), bd(2 * c->nt);
+    for (int t = 0; t < c->nt; ++t) {
+        sd[2 * t] = c->desc[t].support_h;
+        sd[2 * t + 1] = c->desc[t].support_w;
+        bd[2 * t] = c->desc[t].block_h;
+        bd[2 * t + 1] = c->desc[t].block_w;
+    }
+    if ((rc = dev_alloc(c, &c->sdim, sd.size()))) return rc;
+    if ((rc = dev_alloc(c, &c->bdim, bd.size()))) return rc;
+    HIP_TRY(c, hipMemcpy(c->sdim, sd.data(), sd.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->bdim, bd.data(), bd.size() * 4, hipMemcpyHostToDevice));
     if ((rc = dev_alloc(c, &c->pd_support, pds.size()))) return rc;
     if ((rc = dev_alloc(c, &c->pd_block, pdb.size()))) return rc;
     if ((rc = dev_alloc(c, &c->tw, tw.size()))) return rc;
@@ -553,6 +571,9 @@ int alloc_state(deblur_ctx* c) {
     if ((rc = dev_alloc(c, &c->maxW, c->nt))) return rc;
     if ((rc = dev_alloc(c, &c->rowsum, c->nt))) return rc;
     if ((rc = dev_alloc(c, &c->y_glob, (size_t)c->p.M_y * c->p.M_x))) return rc;
+    if ((rc = dev_alloc(c, &c->tile_scale, c->nt))) return rc;
+    if ((rc = dev_alloc(c, &c->gmap, 2 * (size_t)c->nt))) return rc;
+    if ((rc = dev_alloc(c, &c->use_cnn, c->nt))) return rc;
     HIP_TRY(c, hipHostMalloc((void**)&c->h_pinned, 64 * sizeof(double), hipHostMallocDefault));
     // zero everything that is read before being written
     for (float* f : {c->x[0], c->x[1], c->u, c->frame_tmp, c->frame_tmp2})
@@ -987,6 +1008,421 @@ int deblur_debug_fft(int32_t n, int32_t batch, int32_t which, const float* in, f
     if (rc) return fail(nullptr, rc, tmp.err);
     if (e != hipSuccess) return fail(nullptr, DEBLUR_E_HIP, hipGetErrorString(e));
     return DEBLUR_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Warm-start network (host side)
+// ===========================================================================
+
+struct deblur_cnn {
+    hipStream_t stream = nullptr;
+    int maxB = 0, maxH = 0, maxW = 0;
+    std::string err;
+    float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    unsigned short *wf2 = nullptr, *wb2 = nullptr, *wf3 = nullptr, *wb3 = nullptr;
+    float *w1 = nullptr, *w4 = nullptr;
+    dbl::cnn::ImgDesc* desc = nullptr;
+    unsigned short *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *dpA = nullptr, *dpB = nullptr;
+    float *out = nullptr, *dout = nullptr;
+    float *part = nullptr, *red0 = nullptr, *red1 = nullptr;
+    size_t max_chunks = 0;
+    double* loss_part = nullptr;
+    size_t max_loss_parts = 0;
+    int step = 0;
+    std::vector<void*> allocs;
+};
+
+namespace {
+
+int cfail(deblur_cnn* n, int code, const std::string& msg) {
+    if (n) n->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+#define HIP_TRY_N(net, call)                                                                       \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return cfail((net), DEBLUR_E_HIP, std::string(#call ": ") + hipGetErrorString(e_));    \
+    } while (0)
+
+template <class T>
+int net_alloc(deblur_cnn* n, T** ptr, size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        return cfail(n, DEBLUR_E_OOM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n->allocs.push_back(p);
+    *ptr = static_cast<T*>(p);
+    return DEBLUR_OK;
+}
+
+int net_check(deblur_cnn* n, const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return cfail(n, DEBLUR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return DEBLUR_OK;
+}
+
+namespace K = dbl::cnn;
+
+dim3 pix_grid_cnn(int B, int H, int W) { return dim3((W + 255) / 256, H, B); }
+
+int net_set_desc(deblur_cnn* n, int B, int H, int W, const int32_t* valid) {
+    std::vector<K::ImgDesc> d(B);
+    for (int b = 0; b < B; ++b) {
+        d[b].vh = valid ? std::min<int>(valid[2 * b], H) : H;
+        d[b].vw = valid ? std::min<int>(valid[2 * b + 1], W) : W;
+    }
+    HIP_TRY_N(n, hipMemcpyAsync(n->desc, d.data(), B * sizeof(K::ImgDesc), hipMemcpyHostToDevice, n->stream));
+    HIP_TRY_N(n, hipStreamSynchronize(n->stream));   // d is a temporary
+    return DEBLUR_OK;
+}
+
+void net_prep(deblur_cnn* n) {
+    hipLaunchKernelGGL(K::k_prep_weights, dim3((K::kMidBf16 + 255) / 256), dim3(256), 0, n->stream, n->master, n->wf2,
+                       n->wb2, n->wf3, n->wb3, n->w1, n->w4);
+}
+
+// Forward of B images [B][H][W] (device) -> n->out; activations kept.
+void net_forward(deblur_cnn* n, const float* img, int B, int H, int W) {
+    hipLaunchKernelGGL(K::k_conv_in, pix_grid_cnn(B, H, W), dim3(256), 0, n->stream, img, n->desc, H, W, n->w1,
+                       n->master, n->a1);
+    const dim3 mg((W + 63) / 64, H, B);
+    hipLaunchKernelGGL(K::k_conv_mid, mg, dim3(256), 0, n->stream, n->a1, n->desc, H, W, n->wf2, n->master + K::kB2,
+                       nullptr, n->a2);
+    hipLaunchKernelGGL(K::k_conv_mid, mg, dim3(256), 0, n->stream, n->a2, n->desc, H, W, n->wf3, n->master + K::kB3,
+                       nullptr, n->a3);
+    hipLaunchKernelGGL(K::k_conv_out, pix_grid_cnn(B, H, W), dim3(256), 0, n->stream, n->a3, img, n->desc, H, W, n->w4,
+                       n->master, n->out);
+}
+
+// Reduces n->part ([nchunk][ncols]) to one row and scatters it into n->grad.
+void net_reduce(deblur_cnn* n, size_t nchunk, int ncols, int nw, int woff, int nb, int boff, int bsrc) {
+    const float* src = n->part;
+    float* bufs[2] = {n->red0, n->red1};
+    int which = 0;
+    size_t rows = nchunk;
+    do {
+        const size_t G = (rows + 63) / 64;
+        hipLaunchKernelGGL(K::k_colsum, dim3((ncols + 255) / 256, (unsigned)G), dim3(256), 0, n->stream, src, (int)rows,
+                           ncols, 64, bufs[which]);
+        src = bufs[which];
+        which ^= 1;
+        rows = G;
+    } while (rows > 1);
+    hipLaunchKernelGGL(K::k_scatter_grad, dim3((nw + nb + 255) / 256), dim3(256), 0, n->stream, src, nw, woff, nb,
+                       boff, bsrc, n->grad);
+}
+
+// Loss and gradients into n->grad for images / targets [B][H][W].
+int net_loss_grad(deblur_cnn* n, const float* img, const float* target, int B, int H, int W, const int32_t* valid,
+                  double* loss) {
+    int rc = net_set_desc(n, B, H, W, valid);
+    if (rc) return rc;
+    net_prep(n);
+    net_forward(n, img, B, H, W);
+    long long npix = 0;
+    for (int b = 0; b < B; ++b)
+        npix += (long long)(valid ? std::min<int>(valid[2 * b], H) : H) * (valid ? std::min<int>(valid[2 * b + 1], W) : W);
+    const dim3 pg = pix_grid_cnn(B, H, W);
+    const size_t nlp = (size_t)pg.x * pg.y * pg.z;
+    hipLaunchKernelGGL(K::k_loss, pg, dim3(256), 0, n->stream, n->out, target, n->desc, H, W, 1.0f / (float)npix,
+                       n->dout, n->loss_part);
+    const dim3 wg(W / K::kWgCols, H / K::kWgRows, B);
+    const size_t nchunk = (size_t)wg.x * wg.y * wg.z;
+    // layer 4
+    hipLaunchKernelGGL(K::k_wgrad_edge, wg, dim3(256), 0, n->stream, 1, n->a3, n->dout, n->desc, H, W, n->part);
+    net_reduce(n, nchunk, 9 * K::C + K::C, 9 * K::C, K::kW4, 1, K::kB4, 9 * K::C);
+    hipLaunchKernelGGL(K::k_bwd_out, pg, dim3(256), 0, n->stream, n->dout, n->a3, n->desc, H, W, n->w4, n->dpA);
+    // layer 3
+    hipLaunchKernelGGL(K::k_wgrad_mid, wg, dim3(256), 0, n->stream, n->dpA, n->a2, n->desc, H, W, n->part);
+    net_reduce(n, nchunk, 9 * K::C * K::C + K::C, 9 * K::C * K::C, K::kW3, K::C, K::kB3, 9 * K::C * K::C);
+    const dim3 mg((W + 63) / 64, H, B);
+    hipLaunchKernelGGL(K::k_conv_mid, mg, dim3(256), 0, n->stream, n->dpA, n->desc, H, W, n->wb3, nullptr, n->a2,
+                       n->dpB);
+    // layer 2
+    hipLaunchKernelGGL(K::k_wgrad_mid, wg, dim3(256), 0, n->stream, n->dpB, n->a1, n->desc, H, W, n->part);
+    net_reduce(n, nchunk, 9 * K::C * K::C + K::C, 9 * K::C * K::C, K::kW2, K::C, K::kB2, 9 * K::C * K::C);
+    hipLaunchKernelGGL(K::k_conv_mid, mg, dim3(256), 0, n->stream, n->dpB, n->desc, H, W, n->wb2, nullptr, n->a1,
+                       n->dpA);
+    // layer 1
+    hipLaunchKernelGGL(K::k_wgrad_edge, wg, dim3(256), 0, n->stream, 0, n->dpA, img, n->desc, H, W, n->part);
+    net_reduce(n, nchunk, 9 * K::C + K::C, 9 * K::C, K::kW1, K::C, K::kB1, 9 * K::C);
+    rc = net_check(n, "cnn backward");
+    if (rc) return rc;
+    if (loss) {
+        std::vector<double> lp(nlp);
+        HIP_TRY_N(n, hipMemcpyAsync(lp.data(), n->loss_part, nlp * sizeof(double), hipMemcpyDeviceToHost, n->stream));
+        HIP_TRY_N(n, hipStreamSynchronize(n->stream));
+        double s = 0.0;
+        for (double v : lp) s += v;
+        *loss = s / (double)npix;
+        if (!std::isfinite(*loss)) return cfail(n, DEBLUR_E_NONFINITE, "non-finite loss");
+    }
+    return DEBLUR_OK;
+}
+
+int net_shape_ok(deblur_cnn* n, int B, int H, int W) {
+    if (B < 1 || B > n->maxB || H < 1 || H > n->maxH || W < 1 || W > n->maxW)
+        return cfail(n, DEBLUR_E_SHAPE, "batch or image larger than the network was created for");
+    if (H % K::kWgRows || W % K::kWgCols) return cfail(n, DEBLUR_E_SHAPE, "H must be a multiple of 8 and W of 32");
+    return DEBLUR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int deblur_cnn_create(const float* params, int32_t seed, int32_t maxB, int32_t maxH, int32_t maxW, void* stream,
+                      deblur_cnn** out) {
+    if (!out || maxB < 1 || maxH < 8 || maxW < 32) return cfail(nullptr, DEBLUR_E_ARG, "bad argument");
+    *out = nullptr;
+    deblur_cnn* n = new deblur_cnn();
+    n->stream = static_cast<hipStream_t>(stream);
+    n->maxB = maxB;
+    n->maxH = maxH;
+    n->maxW = maxW;
+    const size_t px = (size_t)maxB * maxH * maxW;
+    n->max_chunks = (size_t)maxB * (maxH / K::kWgRows) * ((maxW + K::kWgCols - 1) / K::kWgCols);
+    const size_t ncol = 9 * K::C * K::C + K::C;
+    n->max_loss_parts = (size_t)maxB * maxH * ((maxW + 255) / 256);
+    int rc = 0;
+    if (!rc) rc = net_alloc(n, &n->master, K::kNParams);
+    if (!rc) rc = net_alloc(n, &n->m, K::kNParams);
+    if (!rc) rc = net_alloc(n, &n->v, K::kNParams);
+    if (!rc) rc = net_alloc(n, &n->grad, K::kNParams);
+    if (!rc) rc = net_alloc(n, &n->wf2, K::kMidBf16);
+    if (!rc) rc = net_alloc(n, &n->wb2, K::kMidBf16);
+    if (!rc) rc = net_alloc(n, &n->wf3, K::kMidBf16);
+    if (!rc) rc = net_alloc(n, &n->wb3, K::kMidBf16);
+    if (!rc) rc = net_alloc(n, &n->w1, 9 * K::C);
+    if (!rc) rc = net_alloc(n, &n->w4, 9 * K::C);
+    if (!rc) rc = net_alloc(n, &n->desc, maxB);
+    if (!rc) rc = net_alloc(n, &n->a1, px * K::C);
+    if (!rc) rc = net_alloc(n, &n->a2, px * K::C);
+    if (!rc) rc = net_alloc(n, &n->a3, px * K::C);
+    if (!rc) rc = net_alloc(n, &n->dpA, px * K::C);
+    if (!rc) rc = net_alloc(n, &n->dpB, px * K::C);
+    if (!rc) rc = net_alloc(n, &n->out, px);
+    if (!rc) rc = net_alloc(n, &n->dout, px);
+    if (!rc) rc = net_alloc(n, &n->part, n->max_chunks * ncol);
+    if (!rc) rc = net_alloc(n, &n->red0, ((n->max_chunks + 63) / 64) * ncol);
+    if (!rc) rc = net_alloc(n, &n->red1, ((n->max_chunks + 4095) / 4096 + 1) * ncol);
+    if (!rc) rc = net_alloc(n, &n->loss_part, n->max_loss_parts);
+    if (rc) {
+        g_create_error = n->err;
+        for (void* p : n->allocs) (void)hipFree(p);
+        delete n;
+        return rc;
+    }
+    std::vector<float> w(K::kNParams, 0.f);
+    if (params) {
+        for (int i = 0; i < K::kNParams; ++i) w[i] = params[i];
+    } else {
+        // He initialisation from a counter-free LCG + Box-Muller (deterministic per seed)
+        unsigned long long st = 0x9E3779B97F4A7C15ull ^ (unsigned long long)(uint32_t)seed;
+        auto uni = [&]() {
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            return ((st >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+        };
+        auto gauss = [&]() { return std::sqrt(-2.0 * std::log(uni())) * std::cos(2.0 * M_PI * uni()); };
+        const int offs[4] = {K::kW1, K::kW2, K::kW3, K::kW4}, fan[4] = {9, 9 * K::C, 9 * K::C, 9 * K::C};
+        const int cnt[4] = {9 * K::C, 9 * K::C * K::C, 9 * K::C * K::C, 9 * K::C};
+        for (int l = 0; l < 4; ++l)
+            for (int i = 0; i < cnt[l]; ++i) w[offs[l] + i] = (float)(gauss() * std::sqrt(2.0 / fan[l]) * (l == 3 ? 0.1 : 1.0));
+    }
+    hipError_t e = hipMemcpy(n->master, w.data(), K::kNParams * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(n->m, 0, K::kNParams * 4);
+    if (e == hipSuccess) e = hipMemset(n->v, 0, K::kNParams * 4);
+    if (e != hipSuccess) {
+        g_create_error = hipGetErrorString(e);
+        for (void* p : n->allocs) (void)hipFree(p);
+        delete n;
+        return DEBLUR_E_HIP;
+    }
+    *out = n;
+    return DEBLUR_OK;
+}
+
+void deblur_cnn_destroy(deblur_cnn* n) {
+    if (!n) return;
+    if (n->stream) (void)hipStreamSynchronize(n->stream);
+    for (void* p : n->allocs) (void)hipFree(p);
+    delete n;
+}
+
+const char* deblur_cnn_last_error(const deblur_cnn* n) { return n ? n->err.c_str() : g_create_error.c_str(); }
+
+int deblur_cnn_get_params(deblur_cnn* n, float* params_host) {
+    if (!n || !params_host) return cfail(n, DEBLUR_E_ARG, "null argument");
+    HIP_TRY_N(n, hipMemcpyAsync(params_host, n->master, K::kNParams * 4, hipMemcpyDeviceToHost, n->stream));
+    HIP_TRY_N(n, hipStreamSynchronize(n->stream));
+    return DEBLUR_OK;
+}
+
+int deblur_cnn_set_params(deblur_cnn* n, const float* params_host) {
+    if (!n || !params_host) return cfail(n, DEBLUR_E_ARG, "null argument");
+    HIP_TRY_N(n, hipMemcpyAsync(n->master, params_host, K::kNParams * 4, hipMemcpyHostToDevice, n->stream));
+    HIP_TRY_N(n, hipMemsetAsync(n->m, 0, K::kNParams * 4, n->stream));
+    HIP_TRY_N(n, hipMemsetAsync(n->v, 0, K::kNParams * 4, n->stream));
+    HIP_TRY_N(n, hipStreamSynchronize(n->stream));
+    n->step = 0;
+    return DEBLUR_OK;
+}
+
+int deblur_cnn_forward(deblur_cnn* n, const float* img, const int32_t* valid_host, int32_t B, int32_t H, int32_t W,
+                       float* out) {
+    if (!n || !img || !out) return cfail(n, DEBLUR_E_ARG, "null argument");
+    int rc = net_shape_ok(n, B, H, W);
+    if (!rc) rc = net_set_desc(n, B, H, W, valid_host);
+    if (rc) return rc;
+    net_prep(n);
+    net_forward(n, img, B, H, W);
+    HIP_TRY_N(n, hipMemcpyAsync(out, n->out, (size_t)B * H * W * 4, hipMemcpyDeviceToDevice, n->stream));
+    return net_check(n, "cnn forward");
+}
+
+int deblur_cnn_loss_grad(deblur_cnn* n, const float* img, const float* target, int32_t B, int32_t H, int32_t W,
+                         double* loss_host, float* grad_host) {
+    if (!n || !img || !target) return cfail(n, DEBLUR_E_ARG, "null argument");
+    int rc = net_shape_ok(n, B, H, W);
+    if (!rc) rc = net_loss_grad(n, img, target, B, H, W, nullptr, loss_host);
+    if (rc) return rc;
+    if (grad_host) {
+        HIP_TRY_N(n, hipMemcpyAsync(grad_host, n->grad, K::kNParams * 4, hipMemcpyDeviceToHost, n->stream));
+        HIP_TRY_N(n, hipStreamSynchronize(n->stream));
+    }
+    return DEBLUR_OK;
+}
+
+int deblur_cnn_train_step(deblur_cnn* n, const float* img, const float* target, int32_t B, int32_t H, int32_t W,
+                          float lr, double* loss_host) {
+    if (!n || !img || !target || !(lr > 0.f)) return cfail(n, DEBLUR_E_ARG, "bad argument");
+    int rc = net_shape_ok(n, B, H, W);
+    if (!rc) rc = net_loss_grad(n, img, target, B, H, W, nullptr, loss_host);
+    if (rc) return rc;
+    n->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = (float)(1.0 - std::pow((double)b1, n->step)), c2 = (float)(1.0 - std::pow((double)b2, n->step));
+    hipLaunchKernelGGL(K::k_adam, dim3((K::kNParams + 255) / 256), dim3(256), 0, n->stream, n->master, n->m, n->v,
+                       n->grad, K::kNParams, lr, b1, b2, 1e-8f, c1, c2);
+    return net_check(n, "adam");
+}
+
+int deblur_cnn_time_forward(deblur_cnn* n, const float* img, int32_t B, int32_t H, int32_t W, int32_t reps,
+                            float* ms_host) {
+    if (!n || !img || !ms_host || reps < 1) return cfail(n, DEBLUR_E_ARG, "bad argument");
+    int rc = net_shape_ok(n, B, H, W);
+    if (!rc) rc = net_set_desc(n, B, H, W, nullptr);
+    if (rc) return rc;
+    net_prep(n);
+    hipEvent_t e0, e1, e2;
+    HIP_TRY_N(n, hipEventCreate(&e0));
+    HIP_TRY_N(n, hipEventCreate(&e1));
+    HIP_TRY_N(n, hipEventCreate(&e2));
+    net_forward(n, img, B, H, W);
+    HIP_TRY_N(n, hipEventRecord(e0, n->stream));
+    for (int i = 0; i < reps; ++i) net_forward(n, img, B, H, W);
+    HIP_TRY_N(n, hipEventRecord(e1, n->stream));
+    const dim3 mg((W + 63) / 64, H, B);
+    for (int i = 0; i < reps; ++i)
+        hipLaunchKernelGGL(K::k_conv_mid, mg, dim3(256), 0, n->stream, n->a1, n->desc, H, W, n->wf2,
+                           n->master + K::kB2, nullptr, n->a2);
+    HIP_TRY_N(n, hipEventRecord(e2, n->stream));
+    HIP_TRY_N(n, hipEventSynchronize(e2));
+    float t0 = 0.f, t1 = 0.f;
+    HIP_TRY_N(n, hipEventElapsedTime(&t0, e0, e1));
+    HIP_TRY_N(n, hipEventElapsedTime(&t1, e1, e2));
+    ms_host[0] = t0 / reps;
+    ms_host[1] = t1 / reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    return net_check(n, "cnn timing");
+}
+
+int deblur_warm_inputs(deblur_ctx* c, float* frames, float* scale_host) {
+    if (!c || !frames) return fail(c, DEBLUR_E_ARG, "null argument");
+    if (!c->have_obs) return fail(c, DEBLUR_E_STATE, "deblur_set_observation must come first");
+    hipLaunchKernelGGL(K::k_tile_scale, dim3(c->nt), dim3(256), 0, c->stream, c->yw, c->bdim, c->N, c->r,
+                       c->tile_scale);
+    hipLaunchKernelGGL(K::k_cnn_tile_input, frame_grid(c), dim3(256), 0, c->stream, c->y_glob, c->sorg, c->sdim,
+                       c->tile_scale, c->p.M_y, c->p.M_x, c->N, frames);
+    if (scale_host) {
+        HIP_TRY(c, hipMemcpyAsync(scale_host, c->tile_scale, c->nt * 4, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
+    return check_launch(c, "warm_inputs");
+}
+
+int deblur_init_cnn(deblur_ctx* c, deblur_cnn* n, int32_t* use_cnn_host, int32_t* n_fallback) {
+    if (!c || !n) return fail(c, DEBLUR_E_ARG, "null argument");
+    if (!c->have_obs) return fail(c, DEBLUR_E_STATE, "deblur_set_observation must come first");
+    const int N = c->N;
+    if (n->maxH < N || n->maxW < N) return fail(c, DEBLUR_E_SHAPE, "network buffers smaller than the FFT frame");
+    if (n->stream != c->stream) return fail(c, DEBLUR_E_ARG, "network and context must share a stream");
+    hipStream_t s = c->stream;
+    const size_t NN = (size_t)N * N;
+    // network input: y at the nearest observed pixel / s_t on each support
+    hipLaunchKernelGGL(K::k_tile_scale, dim3(c->nt), dim3(256), 0, s, c->yw, c->bdim, N, c->r, c->tile_scale);
+    hipLaunchKernelGGL(K::k_cnn_tile_input, frame_grid(c), dim3(256), 0, s, c->y_glob, c->sorg, c->sdim,
+                       c->tile_scale, c->p.M_y, c->p.M_x, N, c->frame_tmp2);
+    net_prep(n);
+    std::vector<int32_t> valid(2 * (size_t)c->nt);
+    for (int t = 0; t < c->nt; ++t) {
+        valid[2 * t] = c->desc[t].support_h;
+        valid[2 * t + 1] = c->desc[t].support_w;
+    }
+    for (int t0 = 0; t0 < c->nt; t0 += n->maxB) {
+        const int B = std::min(n->maxB, c->nt - t0);
+        int rc = net_set_desc(n, B, N, N, valid.data() + 2 * t0);
+        if (rc) return fail(c, rc, n->err);
+        net_forward(n, c->frame_tmp2 + t0 * NN, B, N, N);
+        hipLaunchKernelGGL(K::k_cnn_tile_output, dim3(std::min<int>((int)((NN + 255) / 256), 64), B), dim3(256), 0, s,
+                           n->out, c->tile_scale + t0, c->sdim + 2 * t0, N, c->frame_tmp + t0 * NN);
+    }
+    // plain init (the fallback) into frame_tmp2
+    hipLaunchKernelGGL(dbl::k_init_observed, frame_grid(c), dim3(256), 0, s, c->y_glob, c->tiles, c->sorg, c->p.M_y,
+                       c->p.M_x, N, c->frame_tmp2, c->u);
+    // projected-gradient map norm ||x0 - P(x0 - tau grad f_t(x0))|| per tile for both
+    float* cand[2] = {c->frame_tmp, c->frame_tmp2};
+    for (int k = 0; k < 2; ++k) {
+        hipLaunchKernelGGL(dbl::k_copy, dim3(1024), dim3(256), 0, s, cand[k], c->x[0], frame_elems(c));
+        hipLaunchKernelGGL(dbl::k_copy, dim3(1024), dim3(256), 0, s, cand[k], c->u, frame_elems(c));
+        row_fwd(c, s, c->x[0], c->Zk, 1);
+        inner_step(c, s, 0);
+        hipLaunchKernelGGL(K::k_tile_dist2, dim3(c->nt), dim3(256), 0, s, c->x[1], c->x[0], N, c->gmap + k * c->nt);
+    }
+    std::vector<double> gm(2 * (size_t)c->nt);
+    HIP_TRY(c, hipMemcpyAsync(gm.data(), c->gmap, gm.size() * 8, hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    std::vector<int> use(c->nt);
+    int nf = 0;
+    for (int t = 0; t < c->nt; ++t) {
+        if (!std::isfinite(gm[t]) || !std::isfinite(gm[c->nt + t])) {
+            use[t] = 0;
+        } else {
+            // keep the network's start only if its map norm is >= 0.1% smaller
+            use[t] = std::sqrt(gm[t]) <= 0.999 * std::sqrt(gm[c->nt + t]) ? 1 : 0;
+        }
+        nf += 1 - use[t];
+        if (use_cnn_host) use_cnn_host[t] = use[t];
+    }
+    if (n_fallback) *n_fallback = nf;
+    HIP_TRY(c, hipMemcpyAsync(c->use_cnn, use.data(), c->nt * 4, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(K::k_tile_select, frame_grid(c), dim3(256), 0, s, c->frame_tmp, c->frame_tmp2, c->use_cnn, N,
+                       c->x[0]);
+    hipLaunchKernelGGL(dbl::k_copy, dim3(1024), dim3(256), 0, s, c->x[0], c->u, frame_elems(c));
+    c->cur = 0;
+    refresh_spectra(c, s);
+    c->have_state = true;
+    HIP_TRY(c, hipStreamSynchronize(s));
+    return check_launch(c, "init_cnn");
 }
 
 }  // extern "C"

@@ -1,0 +1,163 @@
+"""Warm-start network on the GPU against the oracle, and its use in the solver."""
+import numpy as np
+import pytest
+
+from oracle import cnn
+
+pytestmark = pytest.mark.gpu
+
+
+def _params(seed, last=0.3):
+    rng = np.random.default_rng(seed)
+    p = cnn.init_params(seed, scale_last=last)
+    p = [(W, 0.05 * rng.standard_normal(b.shape)) for W, b in p]
+    return cnn.flatten(p).astype(np.float32)
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def test_forward_matches_oracle():
+    import torch
+    from paper_1705_06603_amd import _lib as dl
+    flat = _params(1)
+    net = dl.Net(4, 64, 64, params=flat)
+    rng = np.random.default_rng(2)
+    B, H, W = 2, 32, 64
+    img = rng.random((B, H, W)).astype(np.float32)
+    valid = [[32, 64], [30, 50]]
+    out = net.forward(torch.tensor(img, device="cuda"), valid=valid).cpu().numpy()
+    P = cnn.unflatten(flat.astype(np.float64))
+    for b, (vh, vw) in enumerate(valid):
+        x = img[b:b + 1, :vh, :vw].astype(np.float64)
+        ref16, _ = cnn.forward(P, x, bf16=True)
+        ref64, _ = cnn.forward(P, x, bf16=False)
+        assert _rel(out[b, :vh, :vw], ref16[0]) <= 5e-3
+        assert _rel(out[b, :vh, :vw] - x[0], ref16[0] - x[0]) <= 5e-3
+        assert _rel(out[b, :vh, :vw], ref64[0]) <= 3e-2
+        assert np.all(out[b, vh:, :] == 0) and np.all(out[b, :, vw:] == 0)
+    net.close()
+
+
+def test_loss_and_gradients_match_oracle():
+    import torch
+    from paper_1705_06603_amd import _lib as dl
+    flat = _params(3)
+    net = dl.Net(2, 16, 32, params=flat)
+    rng = np.random.default_rng(4)
+    img = rng.random((2, 16, 32)).astype(np.float32)
+    tgt = rng.random((2, 16, 32)).astype(np.float32)
+    loss, g = net.loss_grad(torch.tensor(img, device="cuda"), torch.tensor(tgt, device="cuda"))
+    ref_loss, ref_grads, _ = cnn.loss_and_grads(cnn.unflatten(flat.astype(np.float64)), img.astype(np.float64),
+                                                tgt.astype(np.float64), bf16=True)
+    assert abs(loss - ref_loss) <= 1e-4 * ref_loss
+    G = cnn.unflatten(g.astype(np.float64))
+    for li in range(4):
+        assert _rel(G[li][0], ref_grads[li][0]) <= 5e-3, (li, "W", _rel(G[li][0], ref_grads[li][0]))
+        assert _rel(G[li][1], ref_grads[li][1]) <= 5e-3, (li, "b", _rel(G[li][1], ref_grads[li][1]))
+    net.close()
+
+
+def test_adam_step_matches_oracle():
+    import torch
+    from paper_1705_06603_amd import _lib as dl
+    flat = _params(5)
+    net = dl.Net(2, 16, 32, params=flat)
+    rng = np.random.default_rng(6)
+    img = rng.random((2, 16, 32)).astype(np.float32)
+    tgt = rng.random((2, 16, 32)).astype(np.float32)
+    lr = 1e-3
+    net.train_step(torch.tensor(img, device="cuda"), torch.tensor(tgt, device="cuda"), lr)
+    upd = net.get_params().astype(np.float64) - flat
+    _, grads, _ = cnn.loss_and_grads(cnn.unflatten(flat.astype(np.float64)), img.astype(np.float64),
+                                     tgt.astype(np.float64), bf16=True)
+    p1, _, _ = cnn.adam_step(flat.astype(np.float64), cnn.flatten(grads), 0.0, 0.0, 1, lr)
+    ref = p1 - flat
+    bad = np.mean(np.abs(upd - ref) > 0.1 * lr)
+    assert bad < 0.01, bad
+    net.close()
+
+
+def test_training_reduces_loss():
+    import torch
+    from paper_1705_06603_amd import _lib as dl
+    net = dl.Net(8, 32, 32, seed=7)
+    rng = np.random.default_rng(8)
+    img = rng.random((8, 32, 32)).astype(np.float32)
+    # target: a 3x3 box blur of the input (a map the network can represent)
+    pad = np.pad(img, ((0, 0), (1, 1), (1, 1)))
+    tgt = sum(pad[:, dy:dy + 32, dx:dx + 32] for dy in range(3) for dx in range(3)) / 9.0
+    ti, tt = torch.tensor(img, device="cuda"), torch.tensor(tgt.astype(np.float32), device="cuda")
+    losses = [net.train_step(ti, tt, 2e-3) for _ in range(80)]
+    assert losses[-1] < 0.3 * losses[0], (losses[0], losses[-1])
+    net.close()
+
+
+def _small_ctx():
+    from tests._gpu import context_of
+    from tests.test_gpu_solver import _mid_problem
+    prob = _mid_problem(seed=9)
+    return context_of(prob), prob
+
+
+def test_warm_start_falls_back_when_network_does_not_help():
+    from paper_1705_06603_amd import _lib as dl
+    ctx, prob = _small_ctx()
+    N = ctx.tiles[0].frame
+    # zero last layer: the network returns its input, i.e. the plain start
+    flat = _params(10)
+    P = cnn.unflatten(flat.astype(np.float64))
+    P[3] = (np.zeros_like(P[3][0]), np.zeros_like(P[3][1]))
+    net = dl.Net(ctx.n_tiles, N, N, params=cnn.flatten(P))
+    use, nf = ctx.init_cnn(net)
+    assert nf == ctx.n_tiles and not use.any()
+    x_w, _ = ctx.get_state()
+    ctx.init()
+    x_p, _ = ctx.get_state()
+    assert np.array_equal(x_w.cpu().numpy(), x_p.cpu().numpy())
+    # a network with exploding output: every tile falls back
+    P[3] = (np.ones_like(P[3][0]) * 50.0, np.ones_like(P[3][1]) * 50.0)
+    net.set_params(cnn.flatten(P))
+    use, nf = ctx.init_cnn(net)
+    assert nf == ctx.n_tiles
+    net.close()
+    ctx.close()
+
+
+def test_trained_warm_start_gains_over_plain_start():
+    """Train briefly on plain-solver pairs of the 256x256 workload, then on a
+    held-out scene the network start is closer to the converged solution
+    than the plain start, and the solve reaches a residual sooner."""
+    from paper_1705_06603_amd import _lib as dl
+    from paper_1705_06603_amd import train as tr
+    from paper_1705_06603_amd import workloads
+    w = workloads.WORKLOADS["small"]
+    ctx, _ = tr.workload_context(w)
+    N = ctx.tiles[0].frame
+    ins, outs = tr.make_pairs(ctx, w, seeds=range(100, 108), crop=128, crops_per_tile=4, n_outer=15)
+    net = dl.Net(16, N, N, seed=11)
+    losses = tr.train(net, ins, outs, steps=250, batch=16, lr=2e-3)
+    assert losses[-1] < losses[0]
+    # held-out scene
+    tr.observe_scene(ctx, w, 999)
+    ctx.init()
+    ctx.run(30, w.n_inner)
+    x_star, _ = ctx.get_state()
+    x_star = x_star.cpu().numpy()
+    ctx.init()
+    x_plain, _ = ctx.get_state()
+    use, nf = ctx.init_cnn(net)
+    x_warm, _ = ctx.get_state()
+    d_plain = np.linalg.norm(x_plain.cpu().numpy() - x_star)
+    d_warm = np.linalg.norm(x_warm.cpu().numpy() - x_star)
+    print(f"distance to solution: plain {d_plain:.4e} warm {d_warm:.4e}, tiles kept {int(use.sum())}/{len(use)}")
+    assert d_warm < d_plain
+    res_w = ctx.run(5, w.n_inner)
+    ctx.init()
+    res_p = ctx.run(5, w.n_inner)
+    print("residuals warm", res_w, "plain", res_p)
+    net.close()
+    ctx.close()
