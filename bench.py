@@ -121,6 +121,64 @@ def cpu_baseline(scene, psfs, y, W, w, budget_s=20.0):
                       f"one process); whole-image rate extrapolated by tile count"}
 
 
+def convergence(ctx, w, args):
+    """Time and iterations to a D-R residual of 1e-4 from the plain start and
+    from the network's warm start (with per-tile fallback), same GPU, same
+    scene.  The network is trained first (untimed) on plain-solver pairs of
+    fresh scenes (seeds 10000+), held out from the benchmark scene."""
+    import torch
+    from paper_1705_06603_amd import _lib as dl
+    from paper_1705_06603_amd import train as tr
+    N = ctx.tiles[0].frame
+    t0 = time.perf_counter()
+    tctx, _ = tr.workload_context(w)
+    ins, outs = tr.make_pairs(tctx, w, seeds=range(10000, 10000 + args.train_scenes), crop=256,
+                              crops_per_tile=1, n_outer=w.n_outer)
+    net = dl.Net(max(16, ctx.n_tiles), N, N, seed=3)
+    losses = tr.train(net, ins, outs, steps=args.train_steps, batch=16, lr=2e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    tctx.close()
+    out = {"tol": 1e-4, "n_inner": w.n_inner, "gamma": w.gamma,
+           "training": {"pairs": int(ins.shape[0]), "crop": 256, "steps": args.train_steps, "batch": 16,
+                        "loss_first": losses[0], "loss_last": losses[-1], "seconds": round(train_s, 2)}}
+    max_rounds = args.max_rounds
+    stream = torch.cuda.current_stream()
+    for label in ("plain", "warm"):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        if label == "plain":
+            ctx.init()
+            nf = None
+        else:
+            _, nf = ctx.init_cnn(net)
+        res = ctx.run(max_rounds, w.n_inner, tol=1e-4)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        reached = res[-1] <= 1e-4
+        first = lambda th: next(((i + 1) * w.n_inner for i, r in enumerate(res) if r <= th), None)
+        out[label] = {"reached": bool(reached), "iterations": len(res) * w.n_inner if reached else None,
+                      "ms": round(e0.elapsed_time(e1), 2) if reached else None,
+                      "ms_run": round(e0.elapsed_time(e1), 2), "rounds_run": len(res),
+                      "final_residual": res[-1], "iterations_to_1e-3": first(1e-3),
+                      "iterations_to_1e-2": first(1e-2)}
+        if label == "warm":
+            out[label]["fallback_tiles"] = nf
+    # network inference cost and MFMA utilisation of a 32 -> 32 layer
+    frames, _ = ctx.warm_inputs()
+    B = min(ctx.n_tiles, net.max_batch)
+    ms_all, ms_mid = net.time_forward(frames[:B].contiguous(), reps=10)
+    flop_mid = 2.0 * 9 * 32 * 32 * B * N * N
+    out["network"] = {"forward_ms_per_batch": round(ms_all, 3), "batch_tiles": B, "frame": N,
+                      "mid_layer_ms": round(ms_mid, 4), "mid_layer_TFLOPs": round(flop_mid / (ms_mid * 1e-3) / 1e12, 1),
+                      "mfma_bf16_peak_TFLOPs": 2500.0,
+                      "mfma_utilisation": round(flop_mid / (ms_mid * 1e-3) / 2.5e15, 4)}
+    net.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +186,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-convergence", action="store_true")
+    ap.add_argument("--max-rounds", type=int, default=1500)
+    ap.add_argument("--train-scenes", type=int, default=8)
+    ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -210,6 +272,9 @@ def main():
         "wall_s": round(wall, 3),
         "roofline": roofline,
     }
+    if not args.no_convergence:
+        print("# convergence: plain vs warm start", file=sys.stderr, flush=True)
+        out["convergence"] = convergence(ctx, w, args)
     if not args.no_cpu_baseline:
         print("# cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene, psfs, y, W, w, args.cpu_budget)

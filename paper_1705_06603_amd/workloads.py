@@ -78,15 +78,15 @@ WORKLOADS = {
     # 2048 x 2048, 8 x 8 tiles, 32-px overlap, 8 x 8 Moffat PSFs of 31 x 31.
     "batched": Workload("batched", M=2048, tiles=8, pitch=256, overlap=32, grid=8,
                         psf_size=31, psf_kind="moffat", noise="poisson",
-                        n_iter=200, seed=2),
+                        n_iter=200, gamma=4.0, seed=2),
     # 8192 x 8192, 16 x 16 tiles (512-576 px), 64-px overlap, 63 x 63 Moffat PSFs.
     "large": Workload("large", M=8192, tiles=16, pitch=512, overlap=64, grid=16,
                       psf_size=63, psf_kind="moffat", noise="poisson",
-                      n_iter=300, seed=3),
+                      n_iter=300, gamma=4.0, seed=3),
     # 16384 x 16384, 32 x 32 tiles, 64-px overlap, 63 x 63 Moffat PSFs.
     "combined": Workload("combined", M=16384, tiles=32, pitch=512, overlap=64, grid=32,
                          psf_size=63, psf_kind="moffat", noise="poisson",
-                         n_iter=300, seed=5),
+                         n_iter=300, gamma=4.0, seed=5),
 }
 
 
