@@ -213,8 +213,8 @@ void launch_row_inv(deblur_ctx* c, hipStream_t s, const float2* in, float* out, 
 template <int N>
 void launch_col_H(deblur_ctx* c, hipStream_t s) {
     using C = dbl::Cfg<N>;
-    hipLaunchKernelGGL(dbl::k_col_H<N>, dim3(C::CG, c->nt), dim3(C::NT), 0, s, c->Zk, c->tiles, c->tentY, c->spec,
-                       c->tw, c->Yc);
+    hipLaunchKernelGGL(dbl::k_col_H<N>, dim3(8 * ((C::CG * c->nt + 7) / 8)), dim3(C::NT), 0, s, c->Zk, c->tiles,
+                       c->tentY, c->spec, c->tw, c->Yc, c->nt);
 }
 template <int N>
 void launch_row_resid(deblur_ctx* c, hipStream_t s) {
@@ -225,8 +225,8 @@ void launch_row_resid(deblur_ctx* c, hipStream_t s) {
 template <int N>
 void launch_col_Ht(deblur_ctx* c, hipStream_t s) {
     using C = dbl::Cfg<N>;
-    hipLaunchKernelGGL(dbl::k_col_Ht<N>, dim3(C::CG, c->nt), dim3(C::NT), 0, s, c->Rr, c->tiles, c->tentY, c->spec,
-                       c->tw, c->Gk);
+    hipLaunchKernelGGL(dbl::k_col_Ht<N>, dim3(8 * ((C::CG * c->nt + 7) / 8)), dim3(C::NT), 0, s, c->Rr, c->tiles,
+                       c->tentY, c->spec, c->tw, c->Gk, c->nt);
 }
 SolveParams solve_params(const deblur_ctx* c) {
     SolveParams P;
@@ -251,6 +251,22 @@ template <int N>
 void launch_col_fft_dbg(deblur_ctx* c, hipStream_t s, const float2* in, float2* out, int dir) {
     using C = dbl::Cfg<N>;
     hipLaunchKernelGGL(dbl::k_col_fft_dbg<N>, dim3(C::CG, c->nt), dim3(C::NT), 0, s, in, c->tw, out, dir);
+}
+
+template <int N>
+int make_twiddles_n(deblur_ctx* c, hipStream_t s) {
+    int rc = dev_alloc(c, &c->tw, dbl::Cfg<N>::TW_TOTAL);
+    if (rc) return rc;
+    hipLaunchKernelGGL(dbl::k_make_twiddles<N>, dim3(1), dim3(256), 0, s, c->tw);
+    return check_launch(c, "k_make_twiddles");
+}
+
+int make_twiddles(deblur_ctx* c, hipStream_t s) {
+    switch (c->N) {
+        case 160: return make_twiddles_n<160>(c, s);
+        case 320: return make_twiddles_n<320>(c, s);
+        default: return make_twiddles_n<640>(c, s);
+    }
 }
 
 #define DISPATCH_N(c, fn, ...)                                            \
@@ -481,11 +497,9 @@ int upload_tables(deblur_ctx* c, const float* psfs_host) {
         pds[t] = PackDesc{0, 0, d.support_h, d.support_w, (long long)d.x_offset};
         pdb[t] = PackDesc{r, r, d.block_h, d.block_w, (long long)d.y_offset};
     }
-    std::vector<float2> tw(N);
     std::vector<double2> twd(N);
     for (int e = 0; e < N; ++e) {
         const double a = -2.0 * M_PI * (double)e / N;
-        tw[e] = make_float2((float)std::cos(a), (float)std::sin(a));
         twd[e] = make_double2(std::cos(a), std::sin(a));
     }
 
@@ -513,7 +527,7 @@ int upload_tables(deblur_ctx* c, const float* psfs_host) {
     HIP_TRY(c, hipMemcpy(c->bdim, bd.data(), bd.size() * 4, hipMemcpyHostToDevice));
     if ((rc = dev_alloc(c, &c->pd_support, pds.size()))) return rc;
     if ((rc = dev_alloc(c, &c->pd_block, pdb.size()))) return rc;
-    if ((rc = dev_alloc(c, &c->tw, tw.size()))) return rc;
+    if ((rc = make_twiddles(c, c->stream))) return rc;
     HIP_TRY(c, hipMemcpy(c->tiles, c->tiles_h.data(), c->nt * sizeof(TileInfo), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->tentY, tY.data(), tY.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->tentX, tX.data(), tX.size() * 4, hipMemcpyHostToDevice));
@@ -526,7 +540,6 @@ int upload_tables(deblur_ctx* c, const float* psfs_host) {
     HIP_TRY(c, hipMemcpy(c->xorg, xo.data(), xo.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->pd_support, pds.data(), pds.size() * sizeof(PackDesc), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->pd_block, pdb.data(), pdb.size() * sizeof(PackDesc), hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
 
     // PSF spectra
     float* psf_d = nullptr;
@@ -977,19 +990,13 @@ int deblur_debug_fft(int32_t n, int32_t batch, int32_t which, const float* in, f
         ti[t].nky = ti[t].nkx = 1;
     }
     std::vector<float> ones((size_t)dbl::kMaxK * n, 1.0f);
-    std::vector<float2> tw(n);
-    for (int e = 0; e < n; ++e) {
-        const double a = -2.0 * M_PI * (double)e / n;
-        tw[e] = make_float2((float)std::cos(a), (float)std::sin(a));
-    }
     int rc = dev_alloc(&tmp, &tmp.tiles, batch);
     if (!rc) rc = dev_alloc(&tmp, &tmp.tentX, ones.size());
-    if (!rc) rc = dev_alloc(&tmp, &tmp.tw, tw.size());
+    if (!rc) rc = make_twiddles(&tmp, s);
     hipError_t e = hipSuccess;
     if (!rc) {
         e = hipMemcpy(tmp.tiles, ti.data(), batch * sizeof(TileInfo), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(tmp.tentX, ones.data(), ones.size() * 4, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(tmp.tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice);
     }
     if (!rc && e == hipSuccess) {
         if (which == 0) {

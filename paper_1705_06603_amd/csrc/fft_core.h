@@ -13,10 +13,13 @@
 // (j / Ns) Ns R + (j mod Ns) + r Ns.  After the last pass the line is in
 // natural order.
 //
+// Lane mapping: each line is owned by LPL = n / 20 consecutive lanes (a power
+// of two for every supported n), so lane l works on line q = l / LPL only and
+// its butterflies of a radix-R pass are j = (l mod LPL) + LPL b, b < 20/R.
 // Register layout "L_R" (the input layout of a radix-R first pass, which is
 // also the output layout of a radix-R last pass): lane l, slot b*R + r holds
-// element j + r n/R of line q, where bid = l + 64 b, q = bid / (n/R),
-// j = bid mod (n/R).  The forward plan starts with radix 5 and the inverse
+// element j + r n/R of line q.  LDS and global addresses of a lane are one
+// per-lane base plus compile-time offsets.  The forward plan starts with radix 5 and the inverse
 // plan is the forward plan reversed, so a forward transform's output layout
 // is the inverse transform's input layout and vice versa: a spectrum can be
 // multiplied and transformed back without touching LDS.
@@ -116,33 +119,90 @@ constexpr int pass_radix() {
 template <int n, int DIR> constexpr int first_radix() { return pass_radix<n, DIR, 0>(); }
 template <int n, int DIR> constexpr int last_radix() { return pass_radix<n, DIR, Plan<n>::np - 1>(); }
 
-// Line stride of the LDS exchange buffers: one padding element per line keeps
-// column-wise (transposed) accesses free of bank conflicts.
-template <int n> constexpr int line_stride() { return n + 1; }
-
-// Position of register slot s = b*R + r in layout L_R for lines of length n.
-template <int n, int R>
-__device__ __forceinline__ void slot_pos(int lane, int s, int& line, int& elem) {
-    constexpr int nR = n / R;
-    const int b = s / R, r = s - (s / R) * R;
-    const int bid = lane + kLanes * b;
-    line = bid / nR;
-    elem = bid - line * nR + r * nR;
+// Line stride (in float2) of the LDS exchange buffers.  It is odd, so the
+// column-wise (transposed) accesses of 16 consecutive lines hit distinct
+// banks.  When fewer than 16 lanes own a line, several lines share one
+// 16-lane LDS access; a stride = 9 (mod 32) puts those lines on disjoint banks.
+template <int n> constexpr int line_stride() { return (n / kV < 16) ? n + 9 : n + 1; }
+constexpr int kLinePad = 0;
+template <int n>
+__device__ __forceinline__ int line_off(int q) {
+    return q * line_stride<n>();
 }
 
-// Runs passes p..np-1.  v holds the input in layout L_{radix of pass p} (for
-// p = 0) and receives the output in layout L_{radix of the last pass}.  sw is
-// the wave's LDS region (1280/n lines of stride line_stride<n>()), tw a
-// twiddle table with tw[TS * e] = exp(-2 pi i e / n).
+// Lanes per line: n = 20 * LPL.
+template <int n> constexpr int lanes_per_line() { return n / kV; }
+
+// Compile-time part of the element index of slot s = b*R + r in layout L_R.
+template <int n, int R> constexpr int slot_const(int s) {
+    return lanes_per_line<n>() * (s / R) + (s % R) * (n / R);
+}
+
+// Position of register slot s in layout L_R for lines of length n.
+template <int n, int R>
+__device__ __forceinline__ void slot_pos(int lane, int s, int& line, int& elem) {
+    constexpr int LPL = lanes_per_line<n>();
+    static_assert((LPL & (LPL - 1)) == 0, "lanes per line must be a power of two");
+    line = lane / LPL;
+    elem = (lane % LPL) + slot_const<n, R>(s);
+}
+
 // Opaque copy of the lane index: address arithmetic derived from it is redone
 // where it is used instead of being hoisted (and kept live) across passes and
-// across the callers' loops, which would cost one VGPR per slot and pass.
+// across the callers' loops, which would cost registers per slot and pass.
 __device__ __forceinline__ int fresh_lane(int lane) {
     asm volatile("" : "+v"(lane));
     return lane;
 }
 
-template <int n, int DIR, int TS, int p = 0, int Ns = 1>
+// Per-pass twiddle tables.  Pass p (radix R, sub-length Ns > 1) of a length-n
+// transform in direction DIR needs W_{Ns R}^{r k} for r in [1, R), k in
+// [0, Ns); they are stored at twiddle_offset<n, DIR, p>() + (r - 1) Ns + k, so
+// lanes with consecutive k read consecutive entries (no LDS bank conflicts).
+// The direction's sign is folded into the table.
+template <int n, int DIR, int p>
+constexpr int pass_ns() {
+    int ns = 1;
+    for (int i = 0; i < p; ++i) ns *= (DIR == kFwd ? Plan<n>::r[i] : Plan<n>::r[Plan<n>::np - 1 - i]);
+    return ns;
+}
+template <int n, int DIR, int p>
+constexpr int twiddle_offset() {
+    int off = 0, ns = 1;
+    for (int i = 0; i < p; ++i) {
+        const int R = (DIR == kFwd ? Plan<n>::r[i] : Plan<n>::r[Plan<n>::np - 1 - i]);
+        if (ns > 1) off += (R - 1) * ns;
+        ns *= R;
+    }
+    return off;
+}
+template <int n, int DIR>
+constexpr int twiddle_count() { return twiddle_offset<n, DIR, Plan<n>::np>(); }
+
+// Fills the tables of one (n, DIR): entry (p, r, k) = exp(DIR 2 pi i r k / (Ns R)), fp64 rounded.
+template <int n, int DIR, int p = 0>
+__device__ void fill_twiddles(float2* __restrict__ out, int tid, int nthreads) {
+    if constexpr (p < Plan<n>::np) {
+        constexpr int R = pass_radix<n, DIR, p>();
+        constexpr int Ns = pass_ns<n, DIR, p>();
+        if constexpr (Ns > 1) {
+            constexpr int off = twiddle_offset<n, DIR, p>();
+            for (int e = tid; e < (R - 1) * Ns; e += nthreads) {
+                const int r = e / Ns + 1, k = e % Ns;
+                double sn, cs;
+                sincospi((double)DIR * 2.0 * (double)(r * k) / (double)(Ns * R), &sn, &cs);
+                out[off + e] = make_float2((float)cs, (float)sn);
+            }
+        }
+        fill_twiddles<n, DIR, p + 1>(out, tid, nthreads);
+    }
+}
+
+// Runs passes p..np-1.  v holds the input in layout L_{radix of pass p} (for
+// p = 0) and receives the output in layout L_{radix of the last pass}.  sw is
+// the wave's LDS region (1280/n lines, line_off<n>), tw the per-pass twiddle
+// tables of (n, DIR).
+template <int n, int DIR, int p = 0, int Ns = 1>
 __device__ __forceinline__ void fft_passes(float2 (&v)[kV], float2* __restrict__ sw,
                                            const float2* __restrict__ tw, int lane_in) {
     constexpr int np = Plan<n>::np;
@@ -151,28 +211,27 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[kV], float2* __restrict__
         constexpr int R = pass_radix<n, DIR, p>();
         constexpr int NB = kV / R;
         constexpr int nR = n / R;
-        constexpr int LS = line_stride<n>();
+        constexpr int LPL = lanes_per_line<n>();
+        const int l = lane % LPL;
+        float2* __restrict__ line = sw + line_off<n>(lane / LPL);
         if constexpr (p > 0) {
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const int bid = lane + kLanes * b;
-                const int q = bid / nR, j = bid - q * nR;
+            for (int b = 0; b < NB; ++b)
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[b * R + r] = sw[q * LS + j + r * nR];
-            }
+                for (int r = 0; r < R; ++r) v[b * R + r] = line[l + LPL * b + r * nR];
         }
+        // j = l + LPL b;  k = j mod Ns;  jd = j / Ns
+        const int lm = l % Ns, ld = l / Ns;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int bid = lane + kLanes * b;
-            const int q = bid / nR, j = bid - q * nR;
             if constexpr (Ns > 1) {
-                const int k = j % Ns;
+                const int cb = LPL * b;
+                int k = lm + cb % Ns;
+                if (k >= Ns) k -= Ns;
+                constexpr int off = twiddle_offset<n, DIR, p>();
+                const float2* __restrict__ tk = tw + off + k;
 #pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    float2 w = tw[TS * (r * k * (n / (Ns * R)))];
-                    if constexpr (DIR == kInv) w.y = -w.y;
-                    v[b * R + r] = cmul(v[b * R + r], w);
-                }
+                for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], tk[(r - 1) * Ns]);
             }
             dft<R, DIR>(&v[b * R]);
         }
@@ -180,28 +239,30 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[kV], float2* __restrict__
             wave_sync();
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
-                const int bid = lane + kLanes * b;
-                const int q = bid / nR, j = bid - q * nR;
-                const int k = j % Ns;
-                const int base = (j / Ns) * Ns * R + k;
+                const int cb = LPL * b;
+                int k = lm + cb % Ns, jd = ld + cb / Ns;
+                if (k >= Ns) {
+                    k -= Ns;
+                    jd += 1;
+                }
+                float2* __restrict__ o = line + jd * (Ns * R) + k;
 #pragma unroll
-                for (int r = 0; r < R; ++r) sw[q * LS + base + r * Ns] = v[b * R + r];
+                for (int r = 0; r < R; ++r) o[r * Ns] = v[b * R + r];
             }
             wave_sync();
         }
-        fft_passes<n, DIR, TS, p + 1, Ns * R>(v, sw, tw, lane_in);
+        fft_passes<n, DIR, p + 1, Ns * R>(v, sw, tw, lane_in);
     }
 }
 
 // Writes v (layout L_R) to the wave's LDS region in natural order.
 template <int n, int R>
 __device__ __forceinline__ void store_natural(const float2 (&v)[kV], float2* __restrict__ sw, int lane) {
-    constexpr int LS = line_stride<n>();
 #pragma unroll
     for (int s = 0; s < kV; ++s) {
         int q, e;
         slot_pos<n, R>(lane, s, q, e);
-        sw[q * LS + e] = v[s];
+        sw[line_off<n>(q) + e] = v[s];
     }
 }
 

@@ -60,8 +60,17 @@ template <int N> struct Cfg {
     static constexpr int CB = W * LwC;       // columns per column workgroup
     static constexpr int RG = N / RB;        // row workgroups per tile
     static constexpr int CG = (N / 2) / CB;  // column workgroups per tile
-    static constexpr int LSR = n + 1;
-    static constexpr int LSC = N + 1;
+    static constexpr int LSR = line_stride<n>();
+    static constexpr int LSC = line_stride<N>();
+    // twiddle tables: column transforms (length N) and row transforms (length n)
+    static constexpr int TWC_F = twiddle_count<N, kFwd>();
+    static constexpr int TWC_I = twiddle_count<N, kInv>();
+    static constexpr int TWR_F = twiddle_count<n, kFwd>();
+    static constexpr int TWR_I = twiddle_count<n, kInv>();
+    static constexpr int TWC = TWC_F + TWC_I;               // column tables, LDS size
+    static constexpr int TWR = TWR_F + TWR_I + n;           // row tables + W_N^f, LDS size
+    static constexpr int RPOST = TWR_F + TWR_I;             // offset of W_N^f in the row tables
+    static constexpr int TW_TOTAL = TWC + TWR;              // global table: [column | row]
     static constexpr size_t SPEC = (size_t)(N / 2) * N;   // complex values of one half-plane
     static constexpr size_t NSPEC = (size_t)(N / 2 + 1) * N;
     static_assert(RG * RB == N && CG * CB == N / 2, "frame does not split into workgroups");
@@ -81,16 +90,16 @@ __device__ __forceinline__ void store_spectrum_T(const float2* __restrict__ sbuf
 #pragma unroll 4
     for (int e = tid; e < C::RB * n; e += C::NT) {
         const int row = e % C::RB, f = e / C::RB;
-        const float2 Z = sbuf[row * C::LSR + f];
+        const float2 Z = sbuf[line_off<n>(row) + f];
         float2 P;
         if (f == 0) {
             P = make_float2(Z.x + Z.y, Z.x - Z.y);
         } else {
-            const float2 Zm = sbuf[row * C::LSR + (n - f)];
+            const float2 Zm = sbuf[line_off<n>(row) + (n - f)];
             // X = (Z + conj Zm)/2 - i W_N^f (Z - conj Zm)/2
             const float2 A = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
             const float2 B = make_float2(0.5f * (Z.x - Zm.x), 0.5f * (Z.y + Zm.y));
-            const float2 wB = cmul(tw[f], B);
+            const float2 wB = cmul(tw[C::RPOST + f], B);
             P = make_float2(A.x + wB.y, A.y - wB.x);
         }
         out[(size_t)f * N + i0 + row] = P;
@@ -98,16 +107,97 @@ __device__ __forceinline__ void store_spectrum_T(const float2* __restrict__ sbuf
 }
 
 // Transposed load of packed half-spectra in[f][i0 + row] into sbuf[row][f].
+// All global loads of a thread are issued before any LDS store, so their
+// latencies overlap instead of being paid once per unrolled group.
 template <int N>
 __device__ __forceinline__ void load_spectrum_T(float2* __restrict__ sbuf, const float2* __restrict__ in,
                                                 int i0, int tid) {
     using C = Cfg<N>;
     constexpr int n = C::n;
-#pragma unroll 4
-    for (int e = tid; e < C::RB * n; e += C::NT) {
+    constexpr int PER = C::RB * n / C::NT;
+    static_assert(PER * C::NT == C::RB * n, "transpose does not divide the workgroup");
+    float2 buf[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = tid + k * C::NT;
         const int row = e % C::RB, f = e / C::RB;
-        sbuf[row * C::LSR + f] = in[(size_t)f * N + i0 + row];
+        buf[k] = in[(size_t)f * N + i0 + row];
     }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = tid + k * C::NT;
+        const int row = e % C::RB, f = e / C::RB;
+        sbuf[line_off<n>(row) + f] = buf[k];
+    }
+}
+
+// Transposed load of packed half-spectra for a row C2R: reads the pair
+// (f, n - f) of each row from in[.][i0 + row] and stores the complex
+// sequence Z = E + i O whose inverse length-n FFT gives (x[2m], x[2m+1]):
+//   E = (X_f + conj X_{n-f}) / 2,  O = (X_f - conj X_{n-f}) W_N^{-f} / 2,
+// with X_0 = Re P_0 (DC) and X_{n} = Im P_0 (Nyquist) from the packed slot 0.
+template <int N>
+__device__ __forceinline__ void load_c2r_T(float2* __restrict__ sbuf, const float2* __restrict__ in,
+                                           const float2* __restrict__ tw, int i0, int tid) {
+    using C = Cfg<N>;
+    constexpr int n = C::n;
+    constexpr int PAIRS = C::RB * (n / 2 + 1);
+    constexpr int PER = (PAIRS + C::NT - 1) / C::NT;
+    float2 xa[PER], xb[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = tid + k * C::NT;
+        if (e < PAIRS) {
+            const int row = e % C::RB, f = e / C::RB;
+            xa[k] = in[(size_t)f * N + i0 + row];
+            xb[k] = in[(size_t)((n - f) % n) * N + i0 + row];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = tid + k * C::NT;
+        if (e < PAIRS) {
+            const int row = e % C::RB, f = e / C::RB;
+            float2* line = sbuf + line_off<n>(row);
+            if (f == 0) {
+                const float2 X = xa[k];
+                line[0] = make_float2(0.5f * (X.x + X.y), 0.5f * (X.x - X.y));
+            } else {
+                const float2 X = xa[k], Xm = xb[k];
+                {
+                    const float2 E = make_float2(0.5f * (X.x + Xm.x), 0.5f * (X.y - Xm.y));
+                    const float2 D = make_float2(0.5f * (X.x - Xm.x), 0.5f * (X.y + Xm.y));
+                    const float2 O = cmulc(D, tw[C::RPOST + f]);
+                    line[f] = make_float2(E.x - O.y, E.y + O.x);
+                }
+                if (f != n - f) {
+                    const float2 E = make_float2(0.5f * (Xm.x + X.x), 0.5f * (Xm.y - X.y));
+                    const float2 D = make_float2(0.5f * (Xm.x - X.x), 0.5f * (Xm.y + X.y));
+                    const float2 O = cmulc(D, tw[C::RPOST + (n - f)]);
+                    line[n - f] = make_float2(E.x - O.y, E.y + O.x);
+                }
+            }
+        }
+    }
+}
+
+// Wave-level inverse row FFT of the wave's rows (Z from load_c2r_T).
+// Result: v[s] = (x[2m], x[2m+1]) in layout L5 of length n, times N/2
+// relative to the normalised inverse (folded into the spectra).
+template <int N>
+__device__ __forceinline__ void row_c2r_ready(float2 (&v)[kV], float2* __restrict__ sw,
+                                              const float2* __restrict__ tw, int lane) {
+    using C = Cfg<N>;
+    constexpr int n = C::n;
+    constexpr int R0 = first_radix<n, kInv>();
+#pragma unroll
+    for (int s = 0; s < kV; ++s) {
+        int q, f;
+        slot_pos<n, R0>(lane, s, q, f);
+        v[s] = sw[line_off<n>(q) + f];
+    }
+    wave_sync();
+    fft_passes<n, kInv>(v, sw, tw + C::TWR_F, lane);
 }
 
 // Wave-level C2R of the wave's rows held in sw (packed half-spectra, natural
@@ -123,19 +213,19 @@ __device__ __forceinline__ void row_c2r_wave(float2 (&v)[kV], float2* __restrict
     for (int s = 0; s < kV; ++s) {
         int q, f;
         slot_pos<n, R0>(lane, s, q, f);
-        const float2 X = sw[q * C::LSR + f];
+        const float2 X = sw[line_off<n>(q) + f];
         if (f == 0) {
             v[s] = make_float2(0.5f * (X.x + X.y), 0.5f * (X.x - X.y));
         } else {
-            const float2 Xm = sw[q * C::LSR + (n - f)];
+            const float2 Xm = sw[line_off<n>(q) + (n - f)];
             const float2 E = make_float2(0.5f * (X.x + Xm.x), 0.5f * (X.y - Xm.y));
             const float2 D = make_float2(0.5f * (X.x - Xm.x), 0.5f * (X.y + Xm.y));
-            const float2 O = cmulc(D, tw[f]);          // D * W_N^{-f}
+            const float2 O = cmulc(D, tw[C::RPOST + f]);   // D * W_N^{-f}
             v[s] = make_float2(E.x - O.y, E.y + O.x);   // E + i O
         }
     }
     wave_sync();
-    fft_passes<n, kInv, 2>(v, sw, tw, lane);
+    fft_passes<n, kInv>(v, sw, tw + C::TWR_F, lane);
 }
 
 // Wave-level forward row FFT of v (layout L5 of length n, packed real pairs)
@@ -144,14 +234,34 @@ template <int N>
 __device__ __forceinline__ void row_fft_wave(float2 (&v)[kV], float2* __restrict__ sw,
                                              const float2* __restrict__ tw, int lane) {
     constexpr int n = Cfg<N>::n;
-    fft_passes<n, kFwd, 2>(v, sw, tw, lane);
+    fft_passes<n, kFwd>(v, sw, tw, lane);
     wave_sync();
     store_natural<n, last_radix<n, kFwd>()>(v, sw, lane);
 }
 
-template <int N>
+// Copies the column (COL) or row twiddle tables of frame N into LDS.
+template <int N, bool COL>
 __device__ __forceinline__ void load_twiddles(float2* __restrict__ tw, const float2* __restrict__ twg, int tid) {
-    for (int e = tid; e < N; e += Cfg<N>::NT) tw[e] = twg[e];
+    using C = Cfg<N>;
+    constexpr int cnt = COL ? C::TWC : C::TWR;
+    const float2* src = twg + (COL ? 0 : C::TWC);
+    for (int e = tid; e < cnt; e += C::NT) tw[e] = src[e];
+}
+
+// Builds the global twiddle tables of frame N (one workgroup).
+template <int N>
+__global__ void k_make_twiddles(float2* __restrict__ twg) {
+    using C = Cfg<N>;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    fill_twiddles<N, kFwd>(twg, tid, nt);
+    fill_twiddles<N, kInv>(twg + C::TWC_F, tid, nt);
+    fill_twiddles<C::n, kFwd>(twg + C::TWC, tid, nt);
+    fill_twiddles<C::n, kInv>(twg + C::TWC + C::TWR_F, tid, nt);
+    for (int f = tid; f < C::n; f += nt) {
+        double sn, cs;
+        sincospi(-2.0 * (double)f / (double)N, &sn, &cs);
+        twg[C::TWC + C::RPOST + f] = make_float2((float)cs, (float)sn);
+    }
 }
 
 // x (frames) -> packed row half-spectra of b_k . x for each mask k of the
@@ -162,11 +272,11 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_fwd(const float* __restrict_
                                                         float2* __restrict__ out, int masked) {
     using C = Cfg<N>;
     constexpr int n = C::n;
-    __shared__ float2 sbuf[C::RB * C::LSR];
-    __shared__ float2 tw[N];
+    __shared__ float2 sbuf[C::RB * C::LSR + kLinePad];
+    __shared__ float2 tw[C::TWR];
     const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    load_twiddles<N>(tw, twg, tid);
+    load_twiddles<N, false>(tw, twg, tid);
     const TileInfo ti = tiles[t];
     const int nk = masked ? ti.nkx : 1;
     const int kstride = masked ? kMaxK : 1;
@@ -180,7 +290,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_fwd(const float* __restrict_
         xv[s] = *reinterpret_cast<const float2*>(xt + (size_t)row * N + 2 * m);
     }
     __syncthreads();
-    float2* sw = sbuf + wave * C::LwR * C::LSR;
+    float2* sw = sbuf + line_off<C::n>(wave * C::LwR);
     for (int k = 0; k < nk; ++k) {
         float2 v[kV];
         const float* bm = tentX + ((size_t)ti.tx * kMaxK + k) * N;
@@ -205,24 +315,24 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_inv(const float2* __restrict
                                                         float* __restrict__ out, int masked) {
     using C = Cfg<N>;
     constexpr int n = C::n;
-    __shared__ float2 sbuf[C::RB * C::LSR];
-    __shared__ float2 tw[N];
+    __shared__ float2 sbuf[C::RB * C::LSR + kLinePad];
+    __shared__ float2 tw[C::TWR];
     const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    load_twiddles<N>(tw, twg, tid);
+    load_twiddles<N, false>(tw, twg, tid);
     const TileInfo ti = tiles[t];
     const int nk = masked ? ti.nkx : 1;
     const int kstride = masked ? kMaxK : 1;
-    float2* sw = sbuf + wave * C::LwR * C::LSR;
+    float2* sw = sbuf + line_off<C::n>(wave * C::LwR);
     float2 acc[kV];
 #pragma unroll
     for (int s = 0; s < kV; ++s) acc[s] = make_float2(0.f, 0.f);
     for (int k = 0; k < nk; ++k) {
         __syncthreads();
-        load_spectrum_T<N>(sbuf, in + ((size_t)t * kstride + k) * C::SPEC, i0, tid);
+        load_c2r_T<N>(sbuf, in + ((size_t)t * kstride + k) * C::SPEC, tw, i0, tid);
         __syncthreads();
         float2 v[kV];
-        row_c2r_wave<N>(v, sw, tw, lane);
+        row_c2r_ready<N>(v, sw, tw, lane);
         const float* bm = tentX + ((size_t)ti.tx * kMaxK + k) * N;
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
@@ -249,6 +359,24 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_inv(const float2* __restrict
 // ---------------------------------------------------------------------------
 // Column kernels
 // ---------------------------------------------------------------------------
+
+// XCD-aware work mapping of the column kernels.  Workgroups are dispatched to
+// the 8 XCDs round-robin by linear id, so workgroup L runs on XCD L mod 8.
+// Item I = (L mod 8) * per + L / 8 gives every XCD a contiguous range of items
+// in column-group-major order: an XCD then works on one or two column groups
+// of all tiles, and that column block of every PSF spectrum (CB columns x N x
+// 8 bytes per node) is shared in its L2 by the up-to-9 tiles that use it.
+// Returns false for padding workgroups (items beyond n_items).
+__device__ __forceinline__ bool col_item(int n_tiles, int n_cg, int& cg, int& t) {
+    const int items = n_tiles * n_cg;
+    const int per = (items + 7) / 8;
+    const int L = blockIdx.x;
+    const int I = (L % 8) * per + L / 8;
+    if (I >= items) return false;
+    cg = I / n_tiles;
+    t = I - cg * n_tiles;
+    return true;
+}
 
 // Loads the spectrum values of one term for the wave's columns, in the
 // forward transform's output layout (prefetched one term ahead).
@@ -303,19 +431,21 @@ __device__ __forceinline__ void spec_mac(float2 (&acc)[kV], const float2 (&v)[kV
 template <int N>
 __global__ __launch_bounds__(Cfg<N>::NT) void k_col_H(const float2* __restrict__ Zk, const TileInfo* __restrict__ tiles,
                                                       const float* __restrict__ tentY, const float2* __restrict__ spec,
-                                                      const float2* __restrict__ twg, float2* __restrict__ Yc) {
+                                                      const float2* __restrict__ twg, float2* __restrict__ Yc,
+                                                      int n_tiles) {
     using C = Cfg<N>;
-    __shared__ float2 lds[C::W * C::LwC * C::LSC];
-    __shared__ float2 tw[N];
+    __shared__ float2 lds[C::W * (C::LwC * C::LSC + kLinePad)];
+    __shared__ float2 tw[C::TWC];
     __shared__ float2 col0[N];
-    const int t = blockIdx.y;
+    int cg, t;
+    if (!col_item(n_tiles, C::CG, cg, t)) return;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int f0 = blockIdx.x * C::CB + wave * C::LwC;
-    load_twiddles<N>(tw, twg, tid);
+    const int f0 = cg * C::CB + wave * C::LwC;
+    load_twiddles<N, true>(tw, twg, tid);
     const TileInfo* tp = tiles + t;
     const int nky = tp->nky, nkx = tp->nkx, ty = tp->ty;
     const int nterm = nky * nkx;
-    float2* sw = lds + wave * C::LwC * C::LSC;
+    float2* sw = lds + wave * (C::LwC * C::LSC + kLinePad);
     float2 acc[kV], sp[kV];
 #pragma unroll
     for (int s = 0; s < kV; ++s) acc[s] = make_float2(0.f, 0.f);
@@ -336,7 +466,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_H(const float2* __restrict__
                 v[s] = cscale(zt[(size_t)q * N + g], am[g]);
             }
         }
-        fft_passes<N, kFwd, 1>(v, sw, tw, lane);
+        fft_passes<N, kFwd>(v, sw, tw, lane);
         const float2* base = spec + (size_t)tp->spec[ky * kMaxK + kx] * C::NSPEC;
         spec_mac<N, false>(acc, v, sp, base, col0, f0, lane);
         if (term + 1 < nterm) {
@@ -344,7 +474,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_H(const float2* __restrict__
             load_spec<N>(sp, spec + (size_t)tp->spec[ky2 * kMaxK + kx2] * C::NSPEC, f0, lane);
         }
     }
-    fft_passes<N, kInv, 1>(acc, sw, tw, lane);
+    fft_passes<N, kInv>(acc, sw, tw + C::TWC_F, lane);
     float2* yt = Yc + (size_t)t * C::SPEC + (size_t)f0 * N;
 #pragma unroll
     for (int s = 0; s < kV; ++s) {
@@ -358,19 +488,21 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_H(const float2* __restrict__
 template <int N>
 __global__ __launch_bounds__(Cfg<N>::NT, 2) void k_col_Ht(const float2* __restrict__ Rr, const TileInfo* __restrict__ tiles,
                                                        const float* __restrict__ tentY, const float2* __restrict__ spec,
-                                                       const float2* __restrict__ twg, float2* __restrict__ Gk) {
+                                                       const float2* __restrict__ twg, float2* __restrict__ Gk,
+                                                       int n_tiles) {
     using C = Cfg<N>;
-    __shared__ float2 lds[C::W * C::LwC * C::LSC];
-    __shared__ float2 tw[N];
+    __shared__ float2 lds[C::W * (C::LwC * C::LSC + kLinePad)];
+    __shared__ float2 tw[C::TWC];
     __shared__ float2 col0[N];
-    const int t = blockIdx.y;
+    int cg, t;
+    if (!col_item(n_tiles, C::CG, cg, t)) return;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int f0 = blockIdx.x * C::CB + wave * C::LwC;
-    load_twiddles<N>(tw, twg, tid);
+    const int f0 = cg * C::CB + wave * C::LwC;
+    load_twiddles<N, true>(tw, twg, tid);
     const TileInfo* tp = tiles + t;
     const int nky = tp->nky, nkx = tp->nkx, ty = tp->ty;
     const int nterm = nky * nkx;
-    float2* sw = lds + wave * C::LwC * C::LSC;
+    float2* sw = lds + wave * (C::LwC * C::LSC + kLinePad);
     float2 S[kV], sp[kV], acc[kV];
     {
         const float2* rt = Rr + (size_t)t * C::SPEC + (size_t)f0 * N;
@@ -383,7 +515,7 @@ __global__ __launch_bounds__(Cfg<N>::NT, 2) void k_col_Ht(const float2* __restri
     }
     load_spec<N>(sp, spec + (size_t)tp->spec[0] * C::NSPEC, f0, lane);
     __syncthreads();
-    fft_passes<N, kFwd, 1>(S, sw, tw, lane);
+    fft_passes<N, kFwd>(S, sw, tw, lane);
     for (int term = 0; term < nterm; ++term) {
         const int kx = term / nky, ky = term - kx * nky;
         if (ky == 0) {
@@ -399,7 +531,7 @@ __global__ __launch_bounds__(Cfg<N>::NT, 2) void k_col_Ht(const float2* __restri
             const int kx2 = (term + 1) / nky, ky2 = term + 1 - kx2 * nky;
             load_spec<N>(sp, spec + (size_t)tp->spec[ky2 * kMaxK + kx2] * C::NSPEC, f0, lane);
         }
-        fft_passes<N, kInv, 1>(v, sw, tw, lane);
+        fft_passes<N, kInv>(v, sw, tw + C::TWC_F, lane);
         const float* am = tentY + ((size_t)ty * kMaxK + ky) * N;
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
@@ -425,14 +557,14 @@ template <int N>
 __global__ __launch_bounds__(Cfg<N>::NT) void k_col_fft_dbg(const float2* __restrict__ in, const float2* __restrict__ twg,
                                                             float2* __restrict__ out, int dir) {
     using C = Cfg<N>;
-    __shared__ float2 lds[C::W * C::LwC * C::LSC];
-    __shared__ float2 tw[N];
+    __shared__ float2 lds[C::W * (C::LwC * C::LSC + kLinePad)];
+    __shared__ float2 tw[C::TWC];
     const int t = blockIdx.y;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int f0 = blockIdx.x * C::CB + wave * C::LwC;
-    load_twiddles<N>(tw, twg, tid);
+    load_twiddles<N, true>(tw, twg, tid);
     __syncthreads();
-    float2* sw = lds + wave * C::LwC * C::LSC;
+    float2* sw = lds + wave * (C::LwC * C::LSC + kLinePad);
     const float2* it = in + (size_t)t * C::SPEC + (size_t)f0 * N;
     float2* ot = out + (size_t)t * C::SPEC + (size_t)f0 * N;
     float2 v[kV];
@@ -443,7 +575,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_fft_dbg(const float2* __rest
             slot_pos<N, first_radix<N, kFwd>()>(lane, s, q, g);
             v[s] = it[(size_t)q * N + g];
         }
-        fft_passes<N, kFwd, 1>(v, sw, tw, lane);
+        fft_passes<N, kFwd>(v, sw, tw, lane);
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
             int q, g;
@@ -457,7 +589,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_fft_dbg(const float2* __rest
             slot_pos<N, first_radix<N, kInv>()>(lane, s, q, g);
             v[s] = it[(size_t)q * N + g];
         }
-        fft_passes<N, kInv, 1>(v, sw, tw, lane);
+        fft_passes<N, kInv>(v, sw, tw + C::TWC_F, lane);
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
             int q, g;
@@ -493,17 +625,18 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_resid(const float2* __restri
                                                           float* __restrict__ obj_part) {
     using C = Cfg<N>;
     constexpr int n = C::n;
-    __shared__ float2 sbuf[C::RB * C::LSR];
-    __shared__ float2 tw[N];
+    __shared__ float2 sbuf[C::RB * C::LSR + kLinePad];
+    __shared__ float2 tw[C::TWR];
     __shared__ float red[C::W];
     const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    load_twiddles<N>(tw, twg, tid);
-    load_spectrum_T<N>(sbuf, Yc + (size_t)t * C::SPEC, i0, tid);
+    load_twiddles<N, false>(tw, twg, tid);
     __syncthreads();
-    float2* sw = sbuf + wave * C::LwR * C::LSR;
+    load_c2r_T<N>(sbuf, Yc + (size_t)t * C::SPEC, tw, i0, tid);
+    __syncthreads();
+    float2* sw = sbuf + line_off<C::n>(wave * C::LwR);
     float2 v[kV];
-    row_c2r_wave<N>(v, sw, tw, lane);
+    row_c2r_ready<N>(v, sw, tw, lane);
     const float4* ywt = reinterpret_cast<const float4*>(yw + (size_t)t * N * N);
     float obj = 0.f;
 #pragma unroll
@@ -560,14 +693,14 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_update(
     constexpr int n = C::n;
     static_assert(C::RB * N * sizeof(float) <= C::RB * C::LSR * sizeof(float2), "LDS view too small");
     static_assert((N * (C::RB / kSeg)) % C::NT == 0, "update tasks do not divide the workgroup");
-    __shared__ float2 sbuf[C::RB * C::LSR];
-    __shared__ float2 tw[N];
+    __shared__ float2 sbuf[C::RB * C::LSR + kLinePad];
+    __shared__ float2 tw[C::TWR];
     float* sg = reinterpret_cast<float*>(sbuf);   // [RB][N] natural view
     const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    load_twiddles<N>(tw, twg, tid);
+    load_twiddles<N, false>(tw, twg, tid);
     const TileInfo ti = tiles[t];
-    float2* sw = sbuf + wave * C::LwR * C::LSR;
+    float2* sw = sbuf + line_off<C::n>(wave * C::LwR);
 
     // ---- phase 1: data gradient H^T r
     {
@@ -576,10 +709,10 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_update(
         for (int s = 0; s < kV; ++s) gd[s] = make_float2(0.f, 0.f);
         for (int kx = 0; kx < ti.nkx; ++kx) {
             __syncthreads();
-            load_spectrum_T<N>(sbuf, Gk + ((size_t)t * kMaxK + kx) * C::SPEC, i0, tid);
+            load_c2r_T<N>(sbuf, Gk + ((size_t)t * kMaxK + kx) * C::SPEC, tw, i0, tid);
             __syncthreads();
             float2 v[kV];
-            row_c2r_wave<N>(v, sw, tw, lane);
+            row_c2r_ready<N>(v, sw, tw, lane);
             const float* bm = tentX + ((size_t)ti.tx * kMaxK + kx) * N;
 #pragma unroll
             for (int s = 0; s < kV; ++s) {
@@ -611,87 +744,98 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_update(
         const int sy = ti.sy, sx = ti.sx;
         const bool circ = P.bc != 0;
         constexpr int SEGS = C::RB / kSeg;
-        for (int task = tid; task < N * SEGS; task += C::NT) {
-            const int c = task % N;
-            const int ia = i0 + (task / N) * kSeg;
-            const bool colin = c < sx;
-            // neighbour columns (wrapped for the circular difference; -1: none)
-            const int cl = c >= 1 ? c - 1 : (circ ? sx - 1 : -1);
-            const int cr = c + 1 < sx ? c + 1 : (circ ? 0 : -1);
-            // rows ia-1 .. ia+kSeg of x at columns (cl, c, cr), all loads in flight at once
-            float X[kSeg + 2][3];
-            float U[kSeg];
+        constexpr int TASKS = N * SEGS / C::NT;   // per thread (5 for every frame size)
+        // Two tasks per step: their loads are issued together.
+        for (int t2 = 0; t2 < TASKS; t2 += 2) {
+            float X[2][kSeg + 2][3];
+            float U[2][kSeg];
+            int cc[2], iaa[2], cll[2], crr[2];
+            bool act[2];
 #pragma unroll
-            for (int j = 0; j < kSeg + 2; ++j) {
-                int rr = ia - 1 + j;
-                if (rr < 0) rr = circ ? sy - 1 : -1;
-                else if (rr >= sy) rr = (circ && rr == sy) ? 0 : -1;
-                const bool ok = colin && rr >= 0;
-                const float* rowp = xt + (size_t)(ok ? rr : 0) * N;
-                X[j][0] = (ok && cl >= 0) ? rowp[cl] : 0.f;
-                X[j][1] = ok ? rowp[c] : 0.f;
-                X[j][2] = (ok && cr >= 0) ? rowp[cr] : 0.f;
-            }
+            for (int h = 0; h < 2; ++h) {
+                act[h] = t2 + h < TASKS;
+                const int task = tid + (t2 + h) * C::NT;
+                const int c = task % N;
+                const int ia = i0 + (task / N) * kSeg;
+                const bool colin = act[h] && c < sx;
+                cc[h] = c;
+                iaa[h] = ia;
+                cll[h] = c >= 1 ? c - 1 : (circ ? sx - 1 : -1);
+                crr[h] = c + 1 < sx ? c + 1 : (circ ? 0 : -1);
 #pragma unroll
-            for (int k = 0; k < kSeg; ++k) {
-                const int i = ia + k;
-                U[k] = (colin && i < sy) ? ut[(size_t)i * N + c] : 0.f;
-            }
-            const float oxc = colin ? ox[c] : 0.f;
-            // vertical term of the row above the segment: qv(ia-1, c)
-            float qv_up = 0.f;
-            if (colin && (ia >= 1 || circ) && ia < sy) {
-                const float gh = cr >= 0 ? X[0][2] - X[0][1] : 0.f;
-                const float gv = X[1][1] - X[0][1];
-                qv_up = reg_scale(gh, gv, P) * gv;
-            }
-#pragma unroll
-            for (int k = 0; k < kSeg; ++k) {
-                const int i = ia + k;
-                float val = 0.f;
-                if (colin && i < sy) {
-                    const bool nxt = (i + 1 < sy) || circ;
-                    const float xm = X[k + 1][1];
-                    const float gh = cr >= 0 ? X[k + 1][2] - xm : 0.f;
-                    const float gv = nxt ? X[k + 2][1] - xm : 0.f;
-                    const float sc = reg_scale(gh, gv, P);
-                    float g = qv_up - sc * (gh + gv);
-                    if (cl >= 0) {
-                        const float xl = X[k + 1][0];
-                        const float ghl = xm - xl;   // column c is the right neighbour of c-1
-                        const float gvl = nxt ? X[k + 2][0] - xl : 0.f;
-                        g += reg_scale(ghl, gvl, P) * ghl;
-                    }
-                    qv_up = sc * gv;
-                    const float alpha = P.gamma * oy[i] * oxc;
-                    const float grad = sg[(i - i0) * N + c] + P.lambda * g + alpha * (xm - U[k]);
-                    val = xm - tt * grad;
-                    if (P.positivity) val = fmaxf(val, 0.f);
+                for (int j = 0; j < kSeg + 2; ++j) {
+                    int rr = ia - 1 + j;
+                    if (rr < 0) rr = circ ? sy - 1 : -1;
+                    else if (rr >= sy) rr = (circ && rr == sy) ? 0 : -1;
+                    const bool ok = colin && rr >= 0;
+                    const float* rowp = xt + (size_t)(ok ? rr : 0) * N;
+                    X[h][j][0] = (ok && cll[h] >= 0) ? rowp[cll[h]] : 0.f;
+                    X[h][j][1] = ok ? rowp[c] : 0.f;
+                    X[h][j][2] = (ok && crr[h] >= 0) ? rowp[crr[h]] : 0.f;
                 }
-                xo[(size_t)i * N + c] = val;
-                sg[(i - i0) * N + c] = val;
+#pragma unroll
+                for (int k = 0; k < kSeg; ++k) {
+                    const int i = ia + k;
+                    U[h][k] = (colin && i < sy) ? ut[(size_t)i * N + c] : 0.f;
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (!act[h]) continue;
+                const int c = cc[h], ia = iaa[h], cl = cll[h], cr = crr[h];
+                const bool colin = c < sx;
+                const float oxc = colin ? ox[c] : 0.f;
+                // vertical term of the row above the segment: qv(ia-1, c)
+                float qv_up = 0.f;
+                if (colin && (ia >= 1 || circ) && ia < sy) {
+                    const float gh = cr >= 0 ? X[h][0][2] - X[h][0][1] : 0.f;
+                    const float gv = X[h][1][1] - X[h][0][1];
+                    qv_up = reg_scale(gh, gv, P) * gv;
+                }
+#pragma unroll
+                for (int k = 0; k < kSeg; ++k) {
+                    const int i = ia + k;
+                    float val = 0.f;
+                    if (colin && i < sy) {
+                        const bool nxt = (i + 1 < sy) || circ;
+                        const float xm = X[h][k + 1][1];
+                        const float gh = cr >= 0 ? X[h][k + 1][2] - xm : 0.f;
+                        const float gv = nxt ? X[h][k + 2][1] - xm : 0.f;
+                        const float sc = reg_scale(gh, gv, P);
+                        float g = qv_up - sc * (gh + gv);
+                        if (cl >= 0) {
+                            const float xl = X[h][k + 1][0];
+                            const float ghl = xm - xl;   // column c is the right neighbour of c-1
+                            const float gvl = nxt ? X[h][k + 2][0] - xl : 0.f;
+                            g += reg_scale(ghl, gvl, P) * ghl;
+                        }
+                        qv_up = sc * gv;
+                        const float alpha = P.gamma * oy[i] * oxc;
+                        const float grad = sg[(i - i0) * N + c] + P.lambda * g + alpha * (xm - U[h][k]);
+                        val = xm - tt * grad;
+                        if (P.positivity) val = fmaxf(val, 0.f);
+                    }
+                    xo[(size_t)i * N + c] = val;
+                }
             }
         }
         __syncthreads();
     }
 
-    // ---- phase 3: forward row spectra of b_k . x_new
-    float2 xv[kV];
-#pragma unroll
-    for (int s = 0; s < kV; ++s) {
-        int q, m;
-        slot_pos<n, 5>(lane, s, q, m);
-        xv[s] = *reinterpret_cast<const float2*>(sg + (wave * C::LwR + q) * N + 2 * m);
-    }
+    // ---- phase 3: forward row spectra of b_k . x_new (x_new re-read from
+    // the frame just written, an L2 hit, rather than held in registers)
+    const float* xw = xn + (size_t)t * N * N + (size_t)i0 * N;
     for (int kx = 0; kx < ti.nkx; ++kx) {
         const float* bm = tentX + ((size_t)ti.tx * kMaxK + kx) * N;
         float2 v[kV];
+        const int ln = fresh_lane(lane);
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
             int q, m;
-            slot_pos<n, 5>(lane, s, q, m);
+            slot_pos<n, 5>(ln, s, q, m);
             const float2 b = *reinterpret_cast<const float2*>(bm + 2 * m);
-            v[s] = make_float2(b.x * xv[s].x, b.y * xv[s].y);
+            const float2 xv = *reinterpret_cast<const float2*>(xw + (wave * C::LwR + q) * N + 2 * m);
+            v[s] = make_float2(b.x * xv.x, b.y * xv.y);
         }
         __syncthreads();
         row_fft_wave<N>(v, sw, tw, lane);
