@@ -213,7 +213,7 @@ void launch_row_inv(deblur_ctx* c, hipStream_t s, const float2* in, float* out, 
 template <int N>
 void launch_col_H(deblur_ctx* c, hipStream_t s) {
     using C = dbl::Cfg<N>;
-    hipLaunchKernelGGL(dbl::k_col_H<N>, dim3(8 * ((C::CG * c->nt + 7) / 8)), dim3(C::NT), 0, s, c->Zk, c->tiles,
+    hipLaunchKernelGGL(dbl::k_col_H<N>, dim3(dbl::col_grid<N>(c->nt)), dim3(C::NT), 0, s, c->Zk, c->tiles,
                        c->tentY, c->spec, c->tw, c->Yc, c->nt);
 }
 template <int N>
@@ -225,7 +225,7 @@ void launch_row_resid(deblur_ctx* c, hipStream_t s) {
 template <int N>
 void launch_col_Ht(deblur_ctx* c, hipStream_t s) {
     using C = dbl::Cfg<N>;
-    hipLaunchKernelGGL(dbl::k_col_Ht<N>, dim3(8 * ((C::CG * c->nt + 7) / 8)), dim3(C::NT), 0, s, c->Rr, c->tiles,
+    hipLaunchKernelGGL(dbl::k_col_Ht<N>, dim3(dbl::col_grid<N>(c->nt)), dim3(C::NT), 0, s, c->Rr, c->tiles,
                        c->tentY, c->spec, c->tw, c->Gk, c->nt);
 }
 SolveParams solve_params(const deblur_ctx* c) {

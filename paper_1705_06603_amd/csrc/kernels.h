@@ -10,11 +10,12 @@
 // f in [0, N/2) (row frequency) and g in [0, N) (column frequency): the
 // row transform of a real frame is taken as a length-N/2 complex FFT of
 // (even + i odd) samples, its DC and Nyquist values (both real) share slot
-// f = 0 as DC + i Nyquist, and the column transform runs along g.  PSF
-// spectra are stored with N/2 + 1 columns: for f in [1, N/2) the plain 2-D
-// DFT scaled by 2/N^2, for f = 0 the pair c1 = (H(g,0) + H(g,N/2))/2 (column
-// 0) and c2 = (H(g,0) - H(g,N/2))/2 (column N/2), so that the packed column
-// obeys  Y0(g) = c1(g) Z0(g) + c2(g) conj(Z0(-g)).
+// f = 0 as DC + i Nyquist, and the column transform runs along g.  The
+// column kernels split packed column 0 back into its two real columns (DC
+// and Nyquist), each transformed as an ordinary column.  PSF spectra are
+// stored with N/2 + 1 columns [node][f][g], f in [0, N/2]: the plain 2-D DFT
+// of the wrap-centred PSF scaled by 2/N^2 (the two inverse transforms'
+// normalisation and the factor of the half-length row transform).
 //
 // One Local-Solver step is four kernels:
 //   col_H      : sum over terms of column FFT(a_ky . Z_kx) x spectrum, inverse column FFT
@@ -360,70 +361,92 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_inv(const float2* __restrict
 // Column kernels
 // ---------------------------------------------------------------------------
 
-// XCD-aware work mapping of the column kernels.  Workgroups are dispatched to
-// the 8 XCDs round-robin by linear id, so workgroup L runs on XCD L mod 8.
-// Item I = (L mod 8) * per + L / 8 gives every XCD a contiguous range of items
-// in column-group-major order: an XCD then works on one or two column groups
-// of all tiles, and that column block of every PSF spectrum (CB columns x N x
-// 8 bytes per node) is shared in its L2 by the up-to-9 tiles that use it.
-// Returns false for padding workgroups (items beyond n_items).
-__device__ __forceinline__ bool col_item(int n_tiles, int n_cg, int& cg, int& t) {
-    const int items = n_tiles * n_cg;
+// Work items of the column kernels.  Item I < n_tiles * n_cg is column group
+// cg = I / n_tiles of tile t = I mod n_tiles (column-group-major).  The packed
+// column 0 of a half-plane carries two real columns, DC (real part) and
+// Nyquist (imaginary part); the wave owning column 0 treats it as the DC
+// column, and n_nyq = ceil(n_tiles / W) extra items give every tile one wave
+// for its Nyquist column (wave w of extra item j serves tile j W + w).  Both
+// are then ordinary complex columns multiplied by their own spectrum column
+// (0 or N/2), so no wave needs the g -> -g exchange of the packed form.
+//
+// XCD-aware mapping: workgroups go to the 8 XCDs round-robin by linear id,
+// so workgroup L runs on XCD L mod 8.  Item I = (L mod 8) * per + L / 8 gives
+// every XCD a contiguous range of items: an XCD then works on one or two
+// column groups of all tiles, and that column block of every PSF spectrum
+// (CB columns x N x 8 bytes per node) is shared in its L2 by the up-to-9
+// tiles that use it.
+struct ColItem {
+    int t;        // tile of this wave
+    int f0;       // first packed column of this wave (0 for a Nyquist wave)
+    bool nyq;     // this wave transforms the Nyquist column of tile t
+    bool valid;   // false: padding workgroup or Nyquist slot beyond the last tile
+};
+
+template <int N>
+__device__ __forceinline__ ColItem col_item(int n_tiles, int wave) {
+    using C = Cfg<N>;
+    const int main_items = n_tiles * C::CG;
+    const int items = main_items + (n_tiles + C::W - 1) / C::W;
     const int per = (items + 7) / 8;
     const int L = blockIdx.x;
     const int I = (L % 8) * per + L / 8;
-    if (I >= items) return false;
-    cg = I / n_tiles;
-    t = I - cg * n_tiles;
-    return true;
+    ColItem it;
+    if (I < main_items) {
+        const int cg = I / n_tiles;
+        it.t = I - cg * n_tiles;
+        it.f0 = cg * C::CB + wave * C::LwC;
+        it.nyq = false;
+        it.valid = true;
+    } else {
+        it.t = (I - main_items) * C::W + wave;
+        it.f0 = 0;
+        it.nyq = true;
+        it.valid = I < items && it.t < n_tiles;
+    }
+    return it;
+}
+
+template <int N>
+constexpr int col_grid(int n_tiles) {
+    using C = Cfg<N>;
+    const int items = n_tiles * C::CG + (n_tiles + C::W - 1) / C::W;
+    return 8 * ((items + 7) / 8);
+}
+
+// Column modes of a lane: 0 an ordinary packed column, 1 the DC column (real
+// part of packed column 0), 2 the Nyquist column (its imaginary part).
+__device__ __forceinline__ int col_mode(const ColItem& it, int line) {
+    return it.nyq ? 2 : ((it.f0 == 0 && line == 0) ? 1 : 0);
+}
+
+__device__ __forceinline__ float2 col_in(float2 z, int mode) {
+    return mode == 0 ? z : make_float2(mode == 1 ? z.x : z.y, 0.f);
+}
+
+// Stores a column value: the whole complex value for an ordinary column, the
+// real part into .x (DC) or .y (Nyquist) of packed column 0 otherwise (the
+// transform of a real column's Hermitian product is real).  A Nyquist wave
+// stores from its line 0 only.
+__device__ __forceinline__ void col_out(float2* __restrict__ p, float2 v, int mode, int line) {
+    if (mode == 0) *p = v;
+    else if (mode == 1) reinterpret_cast<float*>(p)[0] = v.x;
+    else if (line == 0) reinterpret_cast<float*>(p)[1] = v.x;
 }
 
 // Loads the spectrum values of one term for the wave's columns, in the
-// forward transform's output layout (prefetched one term ahead).
+// forward transform's output layout: column f0 + line, or column N/2 on
+// every line of a Nyquist wave.
 template <int N>
-__device__ __forceinline__ void load_spec(float2 (&sp)[kV], const float2* __restrict__ base, int f0, int lane) {
+__device__ __forceinline__ void load_spec(float2 (&sp)[kV], const float2* __restrict__ base, const ColItem& it,
+                                          int lane) {
     constexpr int RL = last_radix<N, kFwd>();
+    const int c0 = it.nyq ? N / 2 : it.f0, ls = it.nyq ? 0 : N;
 #pragma unroll
     for (int s = 0; s < kV; ++s) {
         int q, g;
         slot_pos<N, RL>(lane, s, q, g);
-        sp[s] = base[(size_t)(f0 + q) * N + g];
-    }
-}
-
-// acc += spec . v for the wave's columns; column f = 0 holds the packed
-// DC/Nyquist pair: acc += c1 v + c2 conj(v(-g)) (c1 prefetched in sp,
-// c2 read from the spectrum's column N/2, v(-g) through col0).
-template <int N, bool CONJ>
-__device__ __forceinline__ void spec_mac(float2 (&acc)[kV], const float2 (&v)[kV], const float2 (&sp)[kV],
-                                         const float2* __restrict__ base, float2* __restrict__ col0, int f0,
-                                         int lane) {
-    constexpr int RL = last_radix<N, kFwd>();
-    if (f0 == 0) {   // wave-uniform: this wave owns column 0 as its line 0
-#pragma unroll
-        for (int s = 0; s < kV; ++s) {
-            int q, g;
-            slot_pos<N, RL>(lane, s, q, g);
-            if (q == 0) col0[g] = v[s];
-        }
-        wave_sync();
-#pragma unroll
-        for (int s = 0; s < kV; ++s) {
-            int q, g;
-            slot_pos<N, RL>(lane, s, q, g);
-            if (q == 0) {
-                const float2 vm = cconj(col0[(N - g) % N]);
-                const float2 c2 = base[(size_t)(N / 2) * N + g];
-                if (CONJ) acc[s] = cadd(acc[s], cadd(cmulc(v[s], sp[s]), cmulc(vm, c2)));
-                else acc[s] = cadd(acc[s], cadd(cmul(sp[s], v[s]), cmul(c2, vm)));
-            } else {
-                acc[s] = cadd(acc[s], CONJ ? cmulc(v[s], sp[s]) : cmul(sp[s], v[s]));
-            }
-        }
-        wave_sync();
-    } else {
-#pragma unroll
-        for (int s = 0; s < kV; ++s) acc[s] = cadd(acc[s], CONJ ? cmulc(v[s], sp[s]) : cmul(sp[s], v[s]));
+        sp[s] = base[(size_t)c0 * N + q * ls + g];
     }
 }
 
@@ -434,14 +457,16 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_H(const float2* __restrict__
                                                       const float2* __restrict__ twg, float2* __restrict__ Yc,
                                                       int n_tiles) {
     using C = Cfg<N>;
+    constexpr int LPL = lanes_per_line<N>();
     __shared__ float2 lds[C::W * (C::LwC * C::LSC + kLinePad)];
     __shared__ float2 tw[C::TWC];
-    __shared__ float2 col0[N];
-    int cg, t;
-    if (!col_item(n_tiles, C::CG, cg, t)) return;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int f0 = cg * C::CB + wave * C::LwC;
+    const ColItem it = col_item<N>(n_tiles, wave);
     load_twiddles<N, true>(tw, twg, tid);
+    __syncthreads();
+    if (!it.valid) return;
+    const int t = it.t, line = lane / LPL, mode = col_mode(it, line);
+    const int ls = it.nyq ? 0 : N;    // a Nyquist wave reads column 0 on every line
     const TileInfo* tp = tiles + t;
     const int nky = tp->nky, nkx = tp->nkx, ty = tp->ty;
     const int nterm = nky * nkx;
@@ -450,11 +475,9 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_H(const float2* __restrict__
 #pragma unroll
     for (int s = 0; s < kV; ++s) acc[s] = make_float2(0.f, 0.f);
     // terms kx-major; Z_kx is re-read for every ky (it stays in L2)
-    load_spec<N>(sp, spec + (size_t)tp->spec[0] * C::NSPEC, f0, lane);
-    __syncthreads();
     for (int term = 0; term < nterm; ++term) {
         const int kx = term / nky, ky = term - kx * nky;
-        const float2* zt = Zk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)f0 * N;
+        const float2* zt = Zk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)it.f0 * N;
         const float* am = tentY + ((size_t)ty * kMaxK + ky) * N;
         float2 v[kV];
         {
@@ -463,58 +486,55 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_H(const float2* __restrict__
             for (int s = 0; s < kV; ++s) {
                 int q, g;
                 slot_pos<N, 5>(ln, s, q, g);
-                v[s] = cscale(zt[(size_t)q * N + g], am[g]);
+                v[s] = cscale(col_in(zt[q * ls + g], mode), am[g]);
             }
         }
         fft_passes<N, kFwd>(v, sw, tw, lane);
-        const float2* base = spec + (size_t)tp->spec[ky * kMaxK + kx] * C::NSPEC;
-        spec_mac<N, false>(acc, v, sp, base, col0, f0, lane);
-        if (term + 1 < nterm) {
-            const int kx2 = (term + 1) / nky, ky2 = term + 1 - kx2 * nky;
-            load_spec<N>(sp, spec + (size_t)tp->spec[ky2 * kMaxK + kx2] * C::NSPEC, f0, lane);
-        }
+        load_spec<N>(sp, spec + (size_t)tp->spec[ky * kMaxK + kx] * C::NSPEC, it, fresh_lane(lane));
+#pragma unroll
+        for (int s = 0; s < kV; ++s) acc[s] = cadd(acc[s], cmul(sp[s], v[s]));
     }
     fft_passes<N, kInv>(acc, sw, tw + C::TWC_F, lane);
-    float2* yt = Yc + (size_t)t * C::SPEC + (size_t)f0 * N;
+    float2* yt = Yc + (size_t)t * C::SPEC + (size_t)it.f0 * N;
 #pragma unroll
     for (int s = 0; s < kV; ++s) {
         int q, g;
         slot_pos<N, 5>(lane, s, q, g);
-        yt[(size_t)q * N + g] = acc[s];
+        col_out(yt + q * ls + g, acc[s], mode, q);
     }
 }
 
 // H^T: Gk[kx][f][:] = sum_ky a_ky . IFFT_col( conj(spec_k) . FFT_col(Rr[f][:]) )
 template <int N>
-__global__ __launch_bounds__(Cfg<N>::NT, 2) void k_col_Ht(const float2* __restrict__ Rr, const TileInfo* __restrict__ tiles,
+__global__ __launch_bounds__(Cfg<N>::NT) void k_col_Ht(const float2* __restrict__ Rr, const TileInfo* __restrict__ tiles,
                                                        const float* __restrict__ tentY, const float2* __restrict__ spec,
                                                        const float2* __restrict__ twg, float2* __restrict__ Gk,
                                                        int n_tiles) {
     using C = Cfg<N>;
+    constexpr int LPL = lanes_per_line<N>();
     __shared__ float2 lds[C::W * (C::LwC * C::LSC + kLinePad)];
     __shared__ float2 tw[C::TWC];
-    __shared__ float2 col0[N];
-    int cg, t;
-    if (!col_item(n_tiles, C::CG, cg, t)) return;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int f0 = cg * C::CB + wave * C::LwC;
+    const ColItem it = col_item<N>(n_tiles, wave);
     load_twiddles<N, true>(tw, twg, tid);
+    __syncthreads();
+    if (!it.valid) return;
+    const int t = it.t, line = lane / LPL, mode = col_mode(it, line);
+    const int ls = it.nyq ? 0 : N;
     const TileInfo* tp = tiles + t;
     const int nky = tp->nky, nkx = tp->nkx, ty = tp->ty;
     const int nterm = nky * nkx;
     float2* sw = lds + wave * (C::LwC * C::LSC + kLinePad);
     float2 S[kV], sp[kV], acc[kV];
     {
-        const float2* rt = Rr + (size_t)t * C::SPEC + (size_t)f0 * N;
+        const float2* rt = Rr + (size_t)t * C::SPEC + (size_t)it.f0 * N;
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
             int q, g;
             slot_pos<N, 5>(lane, s, q, g);
-            S[s] = rt[(size_t)q * N + g];
+            S[s] = col_in(rt[q * ls + g], mode);
         }
     }
-    load_spec<N>(sp, spec + (size_t)tp->spec[0] * C::NSPEC, f0, lane);
-    __syncthreads();
     fft_passes<N, kFwd>(S, sw, tw, lane);
     for (int term = 0; term < nterm; ++term) {
         const int kx = term / nky, ky = term - kx * nky;
@@ -522,15 +542,10 @@ __global__ __launch_bounds__(Cfg<N>::NT, 2) void k_col_Ht(const float2* __restri
 #pragma unroll
             for (int s = 0; s < kV; ++s) acc[s] = make_float2(0.f, 0.f);
         }
-        const float2* base = spec + (size_t)tp->spec[ky * kMaxK + kx] * C::NSPEC;
+        load_spec<N>(sp, spec + (size_t)tp->spec[ky * kMaxK + kx] * C::NSPEC, it, fresh_lane(lane));
         float2 v[kV];
 #pragma unroll
-        for (int s = 0; s < kV; ++s) v[s] = make_float2(0.f, 0.f);
-        spec_mac<N, true>(v, S, sp, base, col0, f0, lane);
-        if (term + 1 < nterm) {
-            const int kx2 = (term + 1) / nky, ky2 = term + 1 - kx2 * nky;
-            load_spec<N>(sp, spec + (size_t)tp->spec[ky2 * kMaxK + kx2] * C::NSPEC, f0, lane);
-        }
+        for (int s = 0; s < kV; ++s) v[s] = cmulc(S[s], sp[s]);
         fft_passes<N, kInv>(v, sw, tw + C::TWC_F, lane);
         const float* am = tentY + ((size_t)ty * kMaxK + ky) * N;
 #pragma unroll
@@ -540,12 +555,12 @@ __global__ __launch_bounds__(Cfg<N>::NT, 2) void k_col_Ht(const float2* __restri
             acc[s] = cadd(acc[s], cscale(v[s], am[g]));
         }
         if (ky == nky - 1) {
-            float2* gt = Gk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)f0 * N;
+            float2* gt = Gk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)it.f0 * N;
 #pragma unroll
             for (int s = 0; s < kV; ++s) {
                 int q, g;
                 slot_pos<N, 5>(lane, s, q, g);
-                gt[(size_t)q * N + g] = acc[s];
+                col_out(gt + q * ls + g, acc[s], mode, q);
             }
         }
     }
@@ -1185,15 +1200,8 @@ __global__ void k_psf_spectra(const float* __restrict__ psf, int P, int N, const
             }
             return make_double2(re * scale, im * scale);
         };
-        float2 out;
-        if (f == 0 || f == N / 2) {
-            const double2 h0 = dft(0), hn = dft(N / 2);
-            const double sgn = (f == 0) ? 1.0 : -1.0;
-            out = make_float2((float)(0.5 * (h0.x + sgn * hn.x)), (float)(0.5 * (h0.y + sgn * hn.y)));
-        } else {
-            const double2 v = dft(f);
-            out = make_float2((float)v.x, (float)v.y);
-        }
+        const double2 v = dft(f);
+        const float2 out = make_float2((float)v.x, (float)v.y);
         spec[(size_t)node * nf * N + (size_t)f * N + g] = out;
     }
 }
