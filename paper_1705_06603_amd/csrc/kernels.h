@@ -85,9 +85,10 @@ template <int N> struct Cfg {
 // real rows, in sbuf) as packed half-spectra out[f][i0 + row].
 template <int N>
 __device__ __forceinline__ void store_spectrum_T(const float2* __restrict__ sbuf, const float2* __restrict__ tw,
-                                                 float2* __restrict__ out, int i0, int tid) {
+                                                 float2* __restrict__ out, int i0, int tid_in) {
     using C = Cfg<N>;
     constexpr int n = C::n;
+    const int tid = fresh_lane(tid_in);
 #pragma unroll 4
     for (int e = tid; e < C::RB * n; e += C::NT) {
         const int row = e % C::RB, f = e / C::RB;
@@ -139,9 +140,10 @@ __device__ __forceinline__ void load_spectrum_T(float2* __restrict__ sbuf, const
 // with X_0 = Re P_0 (DC) and X_{n} = Im P_0 (Nyquist) from the packed slot 0.
 template <int N>
 __device__ __forceinline__ void load_c2r_T(float2* __restrict__ sbuf, const float2* __restrict__ in,
-                                           const float2* __restrict__ tw, int i0, int tid) {
+                                           const float2* __restrict__ tw, int i0, int tid_in) {
     using C = Cfg<N>;
     constexpr int n = C::n;
+    const int tid = fresh_lane(tid_in);
     constexpr int PAIRS = C::RB * (n / 2 + 1);
     constexpr int PER = (PAIRS + C::NT - 1) / C::NT;
     float2 xa[PER], xb[PER];
