@@ -38,8 +38,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def build_workload(seed_offset=0):
-    """Scene, PSFs and the noisy observation of the batched workload.
+def build_workload(tune=True):
+    """Scene, PSFs and the noisy observation of the batched workload, on a
+    context whose launch plan comes from the library's autotuner.
 
     The blur is applied by the HIP library itself (deblur_blur_global);
     noise and weights come from the seeded generators."""
@@ -51,13 +52,20 @@ def build_workload(seed_offset=0):
     scene, psfs = workloads.make_workload(w)
     params = dl.make_params(w.M, w.tiles, w.pitch, w.overlap, w.grid, w.psf_size,
                             lam=w.lam, reg_param=w.eps, gamma=w.gamma, rho=w.rho)
+    trials = []
+    plan = None
+    if tune:
+        plan, trials = dl.autotune(params, psfs, n_inner=w.n_inner, reps=3)
+        params.fft_size = plan.frame
     ctx = dl.Context(params, psfs)
+    if plan is not None:
+        ctx.set_plan(plan)
     x_dev = torch.tensor(scene.astype(np.float32), device="cuda")
     blurred = ctx.blur_global(x_dev).cpu().numpy().astype(np.float64)
     y, W = workloads.observe(blurred, w.noise, w.seed)
     ctx.set_observation(torch.tensor(y.astype(np.float32), device="cuda"),
                         torch.tensor(W.astype(np.float32), device="cuda"))
-    return ctx, w, scene, psfs, y, W
+    return ctx, w, scene, psfs, y, W, trials
 
 
 def tile_bytes(ctx):
@@ -187,6 +195,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-convergence", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the context's default launch plan")
     ap.add_argument("--max-rounds", type=int, default=1500)
     ap.add_argument("--train-scenes", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=300)
@@ -209,7 +218,7 @@ def main():
         return
 
     print("# building workload", file=sys.stderr, flush=True)
-    ctx, w, scene, psfs, y, W = build_workload()
+    ctx, w, scene, psfs, y, W, trials = build_workload(tune=not args.no_autotune)
     n_outer, n_inner = w.n_outer, w.n_inner
     stream = torch.cuda.current_stream()
 
@@ -267,11 +276,18 @@ def main():
                                "8x8 grid of 31x31 Moffat PSFs, Poisson+read noise, smoothed TV + positivity, "
                                "200 iterations (20 D-R rounds x 10 Local-Solver steps), one solve per step",
                    "global_pixels": w.M * w.M, "iterations": iters, "tiles": ctx.n_tiles,
-                   "fft_frame": ctx.tiles[0].frame, "parallelism": "single GPU, all tiles batched"},
+                   "fft_frame": ctx.tiles[0].frame, "parallelism": "single GPU, all tiles batched",
+                   "plan": ctx.plan().as_dict()},
         "final_residual": res[-1] if res else None,
         "wall_s": round(wall, 3),
         "roofline": roofline,
     }
+    if trials:
+        dflt = trials[0]   # the tuner measures a new context's own plan first
+        best = min(trials, key=lambda t: t.us_per_iter)
+        out["autotune"] = {"plans_measured": len(trials), "frames": sorted({t.frame for t in trials}),
+                           "best": best.as_dict(), "default": dflt.as_dict(),
+                           "worst_us_per_iter": round(max(t.us_per_iter for t in trials), 2)}
     if not args.no_convergence:
         print("# convergence: plain vs warm start", file=sys.stderr, flush=True)
         out["convergence"] = convergence(ctx, w, args)

@@ -198,6 +198,71 @@ int deblur_blur_global(deblur_ctx* ctx, const float* x_global, float* y_global);
 enum { DEBLUR_N_KERNELS = 5 };
 int deblur_time_kernels(deblur_ctx* ctx, int32_t reps, float* ms_host);
 
+/* ---------------------------------------------------------------------------
+ * Launch plans and the autotuner.  The per-iteration work of Algorithm 1
+ * (all tiles' Local-Solver steps, then the consensus step) is the same
+ * whatever the plan; the plan only decides how it is laid onto the GPU:
+ *   frame       FFT frame N (any supported N >= the largest support gives
+ *               the same operator, Section II-B's circular embedding);
+ *               fixed when the context is created (params.fft_size);
+ *   col_waves   waves per workgroup of the column-transform kernels;
+ *   row_waves   waves per workgroup of the row-transform kernels;
+ *               each one of two shapes the frame allows: {1, 2} for N = 160,
+ *               {2, 4} for N = 320 and 640;
+ *   tile_order  order in which the column kernels' work items (tiles x
+ *               column groups) are laid over the GPU's 8 XCDs:
+ *               DEBLUR_ORDER_COLUMN_MAJOR  a column group of all tiles per
+ *                                          XCD (PSF spectra shared in L2),
+ *               DEBLUR_ORDER_TILE_MAJOR    whole tiles per XCD,
+ *               DEBLUR_ORDER_HEAVY_FIRST   column-group-major over the tiles
+ *                                          sorted by PSF term count, most
+ *                                          first.
+ * The iterates are bitwise identical under every plan: each pixel goes
+ * through the same operations in the same order.  Only the grouping of the
+ * partial sums of deblur_objective follows row_waves. */
+enum {
+    DEBLUR_ORDER_COLUMN_MAJOR = 0,
+    DEBLUR_ORDER_TILE_MAJOR = 1,
+    DEBLUR_ORDER_HEAVY_FIRST = 2
+};
+typedef struct deblur_plan {
+    int32_t frame;
+    int32_t col_waves;
+    int32_t row_waves;
+    int32_t tile_order;
+    float us_per_iter;    /* measured microseconds per iteration (all tiles'
+                             Local-Solver step + 1/n_inner of a consensus
+                             step) when the plan comes from deblur_autotune;
+                             0 otherwise                                   */
+} deblur_plan;
+
+/* The context's plan (host out).  A new context starts with the frame it
+ * chose, the larger workgroup shape for both kernel families and
+ * DEBLUR_ORDER_COLUMN_MAJOR. */
+int deblur_get_plan(const deblur_ctx* ctx, deblur_plan* plan_host);
+
+/* Replaces the context's plan (host in).  plan.frame must equal the
+ * context's frame (0 is taken as that frame); waves and order must be among
+ * the values above, else DEBLUR_E_ARG.  Synchronises the context stream and
+ * drops the captured graphs of deblur_run, which are re-captured with the
+ * new shapes on their next use.  State and observation are kept. */
+int deblur_set_plan(deblur_ctx* ctx, const deblur_plan* plan_host);
+
+/* Autotuner.  For the problem (params, psfs_host as for deblur_create) it
+ * creates a scratch context per candidate frame (each supported N >= the
+ * largest support, at most two, the smallest first; params.fft_size, if not
+ * 0, is the only candidate), with a synthetic flat observation, and times
+ * every plan of that frame: reps graph-captured D-R rounds of n_inner
+ * Local-Solver steps each, after one untimed round, between HIP events on
+ * stream.  best_host receives the fastest plan; trials_host (may be NULL),
+ * of capacity cap, receives every plan measured, in the order measured, and
+ * *n_trials_host their number.  All scratch memory is freed before return.
+ * Errors as deblur_create (the scratch contexts' allocations) or
+ * DEBLUR_E_ARG for reps < 1 or n_inner < 1. */
+int deblur_autotune(const deblur_params* params, const float* psfs_host, void* stream, int32_t n_inner,
+                    int32_t reps, deblur_plan* best_host, deblur_plan* trials_host, int32_t cap,
+                    int32_t* n_trials_host);
+
 /* Diagnostic access to the FFT core, one stage at a time (synchronous on
  * stream).  n in {160, 320, 640}; batch frames; all data device fp32,
  * complex values as interleaved (re, im) pairs:

@@ -21,6 +21,9 @@ INIT_ZERO, INIT_OBSERVED, INIT_GIVEN = 0, 1, 2
 N_KERNELS = 5
 KERNEL_NAMES = ("col_H", "row_resid", "col_Ht", "row_update", "consensus")
 
+ORDER_COLUMN_MAJOR, ORDER_TILE_MAJOR, ORDER_HEAVY_FIRST = 0, 1, 2
+ORDER_NAMES = {0: "column_major", 1: "tile_major", 2: "heavy_first"}
+
 ERRORS = {-1: "E_ARG", -2: "E_SHAPE", -3: "E_OOM", -4: "E_HIP", -5: "E_STATE", -6: "E_NONFINITE"}
 
 
@@ -54,6 +57,18 @@ class TileDesc(ctypes.Structure):
         ("n_terms", ctypes.c_int32), ("frame", ctypes.c_int32),
         ("n_terms_y", ctypes.c_int32), ("n_terms_x", ctypes.c_int32),
     ]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [
+        ("frame", ctypes.c_int32), ("col_waves", ctypes.c_int32), ("row_waves", ctypes.c_int32),
+        ("tile_order", ctypes.c_int32), ("us_per_iter", ctypes.c_float),
+    ]
+
+    def as_dict(self):
+        return {"frame": self.frame, "col_waves": self.col_waves, "row_waves": self.row_waves,
+                "tile_order": ORDER_NAMES.get(self.tile_order, self.tile_order),
+                "us_per_iter": round(float(self.us_per_iter), 2)}
 
 
 _lib = None
@@ -100,6 +115,10 @@ def lib():
         "deblur_cnn_time_forward": ([vp, f32p, i32, i32, i32, i32, ctypes.POINTER(ctypes.c_float)], i32),
         "deblur_init_cnn": ([vp, vp, vp, ctypes.POINTER(i32)], i32),
         "deblur_warm_inputs": ([vp, f32p, ctypes.POINTER(ctypes.c_float)], i32),
+        "deblur_get_plan": ([vp, ctypes.POINTER(Plan)], i32),
+        "deblur_set_plan": ([vp, ctypes.POINTER(Plan)], i32),
+        "deblur_autotune": ([ctypes.POINTER(Params), vp, vp, i32, i32, ctypes.POINTER(Plan), ctypes.POINTER(Plan),
+                             i32, ctypes.POINTER(i32)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -120,6 +139,7 @@ def exported_symbols():
         "deblur_cnn_create", "deblur_cnn_destroy", "deblur_cnn_last_error", "deblur_cnn_get_params",
         "deblur_cnn_set_params", "deblur_cnn_forward", "deblur_cnn_loss_grad", "deblur_cnn_train_step",
         "deblur_cnn_time_forward", "deblur_init_cnn", "deblur_warm_inputs",
+        "deblur_get_plan", "deblur_set_plan", "deblur_autotune",
     ]
 
 
@@ -285,6 +305,19 @@ class Context:
         self._check(self._L.deblur_warm_inputs(self._h, _ptr(frames), sc))
         return frames, np.array(sc[:], dtype=np.float64)
 
+    def plan(self):
+        pl = Plan()
+        self._check(self._L.deblur_get_plan(self._h, ctypes.byref(pl)))
+        return pl
+
+    def set_plan(self, plan=None, **fields):
+        """Replace the launch plan (a Plan, or fields changed from the current one)."""
+        pl = self.plan() if plan is None else plan
+        for k, v in fields.items():
+            setattr(pl, k, v)
+        self._check(self._L.deblur_set_plan(self._h, ctypes.byref(pl)))
+        return pl
+
     # -- host-side layout helpers (no method arithmetic) ------------------------
     def pack_support(self, x_global):
         """Support-packed float32 host array from a host image on X."""
@@ -310,6 +343,22 @@ class Context:
 
     def pack_list_block(self, tiles):
         return np.concatenate([np.asarray(a, dtype=np.float32).ravel() for a in tiles])
+
+
+def autotune(params: Params, psfs, n_inner=10, reps=3, stream=None):
+    """Fastest launch plan for the problem and every plan measured (the
+    library's autotuner, on scratch contexts it creates and frees)."""
+    L = lib()
+    psf = np.ascontiguousarray(np.asarray(psfs, dtype=np.float32))
+    best = Plan()
+    cap = 64
+    trials = (Plan * cap)()
+    n = ctypes.c_int32()
+    rc = L.deblur_autotune(ctypes.byref(params), psf.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream),
+                           n_inner, reps, ctypes.byref(best), trials, cap, ctypes.byref(n))
+    if rc != 0:
+        raise DeblurError(rc, L.deblur_last_error(None).decode())
+    return best, [trials[i] for i in range(min(n.value, cap))]
 
 
 def debug_fft(n, which, data, stream=None):

@@ -154,6 +154,10 @@ struct deblur_ctx {
     std::vector<void*> allocs;
     std::map<std::pair<int, int>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_defs;
+    // launch plan (frame fixed at creation; the rest set by deblur_set_plan)
+    deblur_plan plan{};
+    int* perm_id = nullptr;      // tile order tables of the column kernels
+    int* perm_heavy = nullptr;
 };
 
 namespace {
@@ -198,35 +202,38 @@ size_t half_elems(const deblur_ctx* c) { return (size_t)c->nt * (c->N / 2) * c->
 // Launch helpers (dispatch on the frame size)
 // ---------------------------------------------------------------------------
 
-template <int N>
+template <int N, int WV>
 void launch_row_fwd(deblur_ctx* c, hipStream_t s, const float* x, float2* out, int masked) {
-    using C = dbl::Cfg<N>;
-    hipLaunchKernelGGL(dbl::k_row_fwd<N>, dim3(C::RG, c->nt), dim3(C::NT), 0, s, x, c->tiles, c->tentX, c->tw, out,
-                       masked);
+    using C = dbl::Cfg<N, WV>;
+    hipLaunchKernelGGL((dbl::k_row_fwd<N, WV>), dim3(C::RG, c->nt), dim3(C::NT), 0, s, x, c->tiles, c->tentX, c->tw,
+                       out, masked);
 }
-template <int N>
+template <int N, int WV>
 void launch_row_inv(deblur_ctx* c, hipStream_t s, const float2* in, float* out, int masked) {
-    using C = dbl::Cfg<N>;
-    hipLaunchKernelGGL(dbl::k_row_inv<N>, dim3(C::RG, c->nt), dim3(C::NT), 0, s, in, c->tiles, c->tentX, c->tw, out,
-                       masked);
+    using C = dbl::Cfg<N, WV>;
+    hipLaunchKernelGGL((dbl::k_row_inv<N, WV>), dim3(C::RG, c->nt), dim3(C::NT), 0, s, in, c->tiles, c->tentX, c->tw,
+                       out, masked);
 }
-template <int N>
+const int* col_perm(const deblur_ctx* c) {
+    return c->plan.tile_order == DEBLUR_ORDER_HEAVY_FIRST ? c->perm_heavy : c->perm_id;
+}
+template <int N, int WV>
 void launch_col_H(deblur_ctx* c, hipStream_t s) {
-    using C = dbl::Cfg<N>;
-    hipLaunchKernelGGL(dbl::k_col_H<N>, dim3(dbl::col_grid<N>(c->nt)), dim3(C::NT), 0, s, c->Zk, c->tiles,
-                       c->tentY, c->spec, c->tw, c->Yc, c->nt);
+    using C = dbl::Cfg<N, WV>;
+    hipLaunchKernelGGL((dbl::k_col_H<N, WV>), dim3(dbl::col_grid<N, WV>(c->nt)), dim3(C::NT), 0, s, c->Zk, c->tiles,
+                       c->tentY, c->spec, c->tw, c->Yc, c->nt, col_perm(c), c->plan.tile_order);
 }
-template <int N>
+template <int N, int WV>
 void launch_row_resid(deblur_ctx* c, hipStream_t s) {
-    using C = dbl::Cfg<N>;
-    hipLaunchKernelGGL(dbl::k_row_resid<N>, dim3(C::RG, c->nt), dim3(C::NT), 0, s, c->Yc, c->yw, c->tw, c->Rr,
+    using C = dbl::Cfg<N, WV>;
+    hipLaunchKernelGGL((dbl::k_row_resid<N, WV>), dim3(C::RG, c->nt), dim3(C::NT), 0, s, c->Yc, c->yw, c->tw, c->Rr,
                        c->obj_part);
 }
-template <int N>
+template <int N, int WV>
 void launch_col_Ht(deblur_ctx* c, hipStream_t s) {
-    using C = dbl::Cfg<N>;
-    hipLaunchKernelGGL(dbl::k_col_Ht<N>, dim3(dbl::col_grid<N>(c->nt)), dim3(C::NT), 0, s, c->Rr, c->tiles,
-                       c->tentY, c->spec, c->tw, c->Gk, c->nt);
+    using C = dbl::Cfg<N, WV>;
+    hipLaunchKernelGGL((dbl::k_col_Ht<N, WV>), dim3(dbl::col_grid<N, WV>(c->nt)), dim3(C::NT), 0, s, c->Rr, c->tiles,
+                       c->tentY, c->spec, c->tw, c->Gk, c->nt, col_perm(c), c->plan.tile_order);
 }
 SolveParams solve_params(const deblur_ctx* c) {
     SolveParams P;
@@ -240,17 +247,17 @@ SolveParams solve_params(const deblur_ctx* c) {
     P.r = c->r;
     return P;
 }
-template <int N>
+template <int N, int WV>
 void launch_row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn) {
-    using C = dbl::Cfg<N>;
-    hipLaunchKernelGGL(dbl::k_row_update<N>, dim3(C::RG, c->nt), dim3(C::NT), 0, s, c->Gk, xc, c->u, c->tiles,
+    using C = dbl::Cfg<N, WV>;
+    hipLaunchKernelGGL((dbl::k_row_update<N, WV>), dim3(C::RG, c->nt), dim3(C::NT), 0, s, c->Gk, xc, c->u, c->tiles,
                        c->tentX, c->omY, c->omX, c->tau, solve_params(c), c->tw, xn, c->Zk);
 }
 
-template <int N>
+template <int N, int WV>
 void launch_col_fft_dbg(deblur_ctx* c, hipStream_t s, const float2* in, float2* out, int dir) {
-    using C = dbl::Cfg<N>;
-    hipLaunchKernelGGL(dbl::k_col_fft_dbg<N>, dim3(C::CG, c->nt), dim3(C::NT), 0, s, in, c->tw, out, dir);
+    using C = dbl::Cfg<N, WV>;
+    hipLaunchKernelGGL((dbl::k_col_fft_dbg<N, WV>), dim3(C::CG, c->nt), dim3(C::NT), 0, s, in, c->tw, out, dir);
 }
 
 template <int N>
@@ -269,35 +276,46 @@ int make_twiddles(deblur_ctx* c, hipStream_t s) {
     }
 }
 
-#define DISPATCH_N(c, fn, ...)                                            \
-    do {                                                                  \
-        switch ((c)->N) {                                                 \
-            case 160: fn<160>(c, __VA_ARGS__); break;                     \
-            case 320: fn<320>(c, __VA_ARGS__); break;                     \
-            default: fn<640>(c, __VA_ARGS__); break;                      \
-        }                                                                 \
+// Dispatch on the frame size and on the plan's waves per workgroup (W is
+// the column kernels' or the row kernels' count, one of the two shapes the
+// frame allows).
+#define DISPATCH_NW(c, W, fn, ...)                                                              \
+    do {                                                                                        \
+        switch ((c)->N) {                                                                       \
+            case 160:                                                                           \
+                if ((W) == dbl::waves_lo<160>()) fn<160, dbl::waves_lo<160>()>(c, __VA_ARGS__); \
+                else fn<160, dbl::waves_hi<160>()>(c, __VA_ARGS__);                             \
+                break;                                                                          \
+            case 320:                                                                           \
+                if ((W) == dbl::waves_lo<320>()) fn<320, dbl::waves_lo<320>()>(c, __VA_ARGS__);                         \
+                else fn<320, dbl::waves_hi<320>()>(c, __VA_ARGS__);                             \
+                break;                                                                          \
+            default:                                                                            \
+                if ((W) == dbl::waves_lo<640>()) fn<640, dbl::waves_lo<640>()>(c, __VA_ARGS__);                         \
+                else fn<640, dbl::waves_hi<640>()>(c, __VA_ARGS__);                             \
+                break;                                                                          \
+        }                                                                                       \
     } while (0)
 
 void row_fwd(deblur_ctx* c, hipStream_t s, const float* x, float2* out, int masked) {
-    DISPATCH_N(c, launch_row_fwd, s, x, out, masked);
+    DISPATCH_NW(c, c->plan.row_waves, launch_row_fwd, s, x, out, masked);
 }
 void row_inv(deblur_ctx* c, hipStream_t s, const float2* in, float* out, int masked) {
-    DISPATCH_N(c, launch_row_inv, s, in, out, masked);
+    DISPATCH_NW(c, c->plan.row_waves, launch_row_inv, s, in, out, masked);
 }
-void col_H(deblur_ctx* c, hipStream_t s) { DISPATCH_N(c, launch_col_H, s); }
-void row_resid(deblur_ctx* c, hipStream_t s) { DISPATCH_N(c, launch_row_resid, s); }
-void col_Ht(deblur_ctx* c, hipStream_t s) { DISPATCH_N(c, launch_col_Ht, s); }
+void col_H(deblur_ctx* c, hipStream_t s) { DISPATCH_NW(c, c->plan.col_waves, launch_col_H, s); }
+void row_resid(deblur_ctx* c, hipStream_t s) { DISPATCH_NW(c, c->plan.row_waves, launch_row_resid, s); }
+void col_Ht(deblur_ctx* c, hipStream_t s) { DISPATCH_NW(c, c->plan.col_waves, launch_col_Ht, s); }
 void row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn) {
-    DISPATCH_N(c, launch_row_update, s, xc, xn);
+    DISPATCH_NW(c, c->plan.row_waves, launch_row_update, s, xc, xn);
 }
 
-int row_groups(const deblur_ctx* c) {
-    switch (c->N) {
-        case 160: return dbl::Cfg<160>::RG;
-        case 320: return dbl::Cfg<320>::RG;
-        default: return dbl::Cfg<640>::RG;
-    }
-}
+int waves_hi(int N) { return N == 160 ? dbl::waves_hi<160>() : dbl::waves_hi<320>(); }
+int waves_lo(int N) { return waves_hi(N) / 2; }
+
+// Row workgroups per tile under the current plan, and the most any plan uses.
+int row_groups(const deblur_ctx* c) { return c->N / (c->plan.row_waves * (dbl::kPts / (c->N / 2))); }
+int row_groups_max(const deblur_ctx* c) { return c->N / (waves_lo(c->N) * (dbl::kPts / (c->N / 2))); }
 
 dim3 pix_grid(const deblur_ctx* c) {
     return dim3((c->Xx + dbl::kPixBlock - 1) / dbl::kPixBlock, c->Xy);
@@ -362,6 +380,7 @@ int build_layout(deblur_ctx* c, const float* psfs_host) {
         if (!c->N) return fail(nullptr, DEBLUR_E_SHAPE, "tile support larger than the largest frame (640)");
     }
     const int N = c->N;
+    c->plan = deblur_plan{N, waves_hi(N), waves_hi(N), DEBLUR_ORDER_COLUMN_MAJOR, 0.f};
     // PSF checks
     for (int i = 0; i < c->nodes * p.P * p.P; ++i)
         if (!std::isfinite(psfs_host[i])) return fail(nullptr, DEBLUR_E_ARG, "non-finite PSF value");
@@ -525,6 +544,16 @@ int upload_tables(deblur_ctx* c, const float* psfs_host) {
     if ((rc = dev_alloc(c, &c->bdim, bd.size()))) return rc;
     HIP_TRY(c, hipMemcpy(c->sdim, sd.data(), sd.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->bdim, bd.data(), bd.size() * 4, hipMemcpyHostToDevice));
+    // tile orders of the column kernels: identity, and by PSF term count (most first)
+    std::vector<int> pid(c->nt), phv(c->nt);
+    for (int t = 0; t < c->nt; ++t) pid[t] = phv[t] = t;
+    std::stable_sort(phv.begin(), phv.end(), [&](int a, int b) {
+        return c->desc[a].n_terms > c->desc[b].n_terms;
+    });
+    if ((rc = dev_alloc(c, &c->perm_id, c->nt))) return rc;
+    if ((rc = dev_alloc(c, &c->perm_heavy, c->nt))) return rc;
+    HIP_TRY(c, hipMemcpy(c->perm_id, pid.data(), c->nt * 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->perm_heavy, phv.data(), c->nt * 4, hipMemcpyHostToDevice));
     if ((rc = dev_alloc(c, &c->pd_support, pds.size()))) return rc;
     if ((rc = dev_alloc(c, &c->pd_block, pdb.size()))) return rc;
     if ((rc = make_twiddles(c, c->stream))) return rc;
@@ -572,7 +601,7 @@ int alloc_state(deblur_ctx* c) {
     if ((rc = dev_alloc(c, &c->Gk, he * dbl::kMaxK))) return rc;
     if ((rc = dev_alloc(c, &c->Yc, he))) return rc;
     if ((rc = dev_alloc(c, &c->Rr, he))) return rc;
-    if ((rc = dev_alloc(c, &c->obj_part, (size_t)c->nt * row_groups(c)))) return rc;
+    if ((rc = dev_alloc(c, &c->obj_part, (size_t)c->nt * row_groups_max(c)))) return rc;
     const dim3 pg = pix_grid(c);
     c->cons_nparts = (int)(pg.x * pg.y);
     if ((rc = dev_alloc(c, &c->cons_part, c->cons_nparts))) return rc;
@@ -654,6 +683,13 @@ int ensure_graph(deblur_ctx* c, int n_inner, int parity, hipGraphExec_t* out) {
     return DEBLUR_OK;
 }
 
+void drop_graphs(deblur_ctx* c) {
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (hipGraph_t g : c->graph_defs) (void)hipGraphDestroy(g);
+    c->graphs.clear();
+    c->graph_defs.clear();
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -669,8 +705,7 @@ const char* deblur_last_error(const deblur_ctx* ctx) {
 void deblur_destroy(deblur_ctx* c) {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
-    for (hipGraph_t g : c->graph_defs) (void)hipGraphDestroy(g);
+    drop_graphs(c);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -975,6 +1010,124 @@ int deblur_time_kernels(deblur_ctx* c, int32_t reps, float* ms) {
     return check_launch(c, "time_kernels");
 }
 
+int deblur_get_plan(const deblur_ctx* c, deblur_plan* out) {
+    if (!c || !out) return DEBLUR_E_ARG;
+    *out = c->plan;
+    return DEBLUR_OK;
+}
+
+int deblur_set_plan(deblur_ctx* c, const deblur_plan* pl) {
+    if (!c || !pl) return fail(c, DEBLUR_E_ARG, "null argument");
+    const int lo = waves_lo(c->N), hi = waves_hi(c->N);
+    if (pl->frame != 0 && pl->frame != c->N)
+        return fail(c, DEBLUR_E_ARG, "plan frame differs from the context's (" + std::to_string(c->N) + ")");
+    if ((pl->col_waves != lo && pl->col_waves != hi) || (pl->row_waves != lo && pl->row_waves != hi))
+        return fail(c, DEBLUR_E_ARG,
+                    "waves per workgroup must be " + std::to_string(lo) + " or " + std::to_string(hi));
+    if (pl->tile_order < DEBLUR_ORDER_COLUMN_MAJOR || pl->tile_order > DEBLUR_ORDER_HEAVY_FIRST)
+        return fail(c, DEBLUR_E_ARG, "unknown tile order");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->plan = *pl;
+    c->plan.frame = c->N;
+    return DEBLUR_OK;
+}
+
+int deblur_autotune(const deblur_params* params, const float* psfs_host, void* stream, int32_t n_inner,
+                    int32_t reps, deblur_plan* best, deblur_plan* trials, int32_t cap, int32_t* n_trials) {
+    if (!params || !psfs_host || !best || reps < 1 || n_inner < 1 || (trials && cap < 0))
+        return fail(nullptr, DEBLUR_E_ARG, "bad argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // candidate frames: the smallest supported frame that holds every support, and the next one
+    std::vector<int> frames;
+    if (params->fft_size) {
+        frames.push_back(params->fft_size);
+    } else {
+        const int r = params->P / 2;
+        const Axis ay{params->M_y, params->T_y, params->pitch, params->overlap, r, params->G_y};
+        const Axis ax{params->M_x, params->T_x, params->pitch, params->overlap, r, params->G_x};
+        int smax = 0;
+        for (int a = 0; a < params->T_y; ++a) smax = std::max(smax, ay.support_len(a));
+        for (int b = 0; b < params->T_x; ++b) smax = std::max(smax, ax.support_len(b));
+        for (int f : kFrames)
+            if (f >= smax && frames.size() < 2) frames.push_back(f);
+        if (frames.empty()) return fail(nullptr, DEBLUR_E_SHAPE, "tile support larger than the largest frame (640)");
+    }
+    int count = 0;
+    bool have = false;
+    deblur_plan top{};
+    for (size_t fi = 0; fi < frames.size(); ++fi) {
+        deblur_params q = *params;
+        q.fft_size = frames[fi];
+        deblur_ctx* c = nullptr;
+        int rc = deblur_create(&q, psfs_host, stream, &c);
+        if (rc) {
+            if (fi > 0 && rc == DEBLUR_E_OOM) break;   // the larger frame does not fit: keep what we have
+            return rc;
+        }
+        float* y = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        const size_t npix = (size_t)q.M_y * q.M_x;
+        auto cleanup = [&]() {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (y) (void)hipFree(y);
+            deblur_destroy(c);
+        };
+        auto hip_fail = [&](hipError_t e, const char* what) {
+            std::string m = std::string("autotune: ") + what + ": " + hipGetErrorString(e);
+            cleanup();
+            return fail(nullptr, DEBLUR_E_HIP, m);
+        };
+        hipError_t e = hipMalloc(&y, npix * sizeof(float));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            cleanup();
+            if (fi > 0) break;
+            return fail(nullptr, DEBLUR_E_OOM, "autotune: observation buffer");
+        }
+        hipLaunchKernelGGL(dbl::k_fill, dim3(1024), dim3(256), 0, s, y, 0.1f, npix);
+        if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+            return hip_fail(e, "hipEventCreate");
+        rc = deblur_set_observation(c, y, nullptr);
+        if (!rc) rc = deblur_init(c, DEBLUR_INIT_OBSERVED, nullptr);
+        const int lo = waves_lo(c->N), hi = waves_hi(c->N);
+        for (int cw : {hi, lo})
+            for (int rw : {hi, lo})
+                for (int order : {DEBLUR_ORDER_COLUMN_MAJOR, DEBLUR_ORDER_TILE_MAJOR, DEBLUR_ORDER_HEAVY_FIRST}) {
+                    if (rc) break;
+                    deblur_plan pl{c->N, cw, rw, order, 0.f};
+                    rc = deblur_set_plan(c, &pl);
+                    if (!rc) rc = deblur_run(c, 1, n_inner, 0.0, nullptr, nullptr);   // capture + warm
+                    if (rc) break;
+                    if ((e = hipEventRecord(e0, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+                    rc = deblur_run(c, reps, n_inner, 0.0, nullptr, nullptr);
+                    if (rc) break;
+                    if ((e = hipEventRecord(e1, s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+                    if ((e = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+                    float ms = 0.f;
+                    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+                    pl.us_per_iter = 1000.f * ms / ((float)reps * n_inner);
+                    if (trials && count < cap) trials[count] = pl;
+                    ++count;
+                    if (!have || pl.us_per_iter < top.us_per_iter) {
+                        top = pl;
+                        have = true;
+                    }
+                }
+        if (rc) {
+            const std::string m = "autotune: " + c->err;
+            cleanup();
+            return fail(nullptr, rc, m);
+        }
+        cleanup();
+    }
+    if (!have) return fail(nullptr, DEBLUR_E_STATE, "autotune measured no plan");
+    *best = top;
+    if (n_trials) *n_trials = count;
+    return DEBLUR_OK;
+}
+
 int deblur_debug_fft(int32_t n, int32_t batch, int32_t which, const float* in, float* out, void* stream) {
     if (n != 160 && n != 320 && n != 640) return fail(nullptr, DEBLUR_E_ARG, "n must be 160, 320 or 640");
     if (batch < 1 || !in || !out || which < 0 || which > 3) return fail(nullptr, DEBLUR_E_ARG, "bad argument");
@@ -983,6 +1136,7 @@ int deblur_debug_fft(int32_t n, int32_t batch, int32_t which, const float* in, f
     deblur_ctx tmp;
     tmp.N = n;
     tmp.nt = batch;
+    tmp.plan = deblur_plan{n, waves_hi(n), waves_hi(n), DEBLUR_ORDER_COLUMN_MAJOR, 0.f};
     std::vector<TileInfo> ti(batch);
     for (int t = 0; t < batch; ++t) {
         ti[t] = TileInfo{};
@@ -1004,8 +1158,8 @@ int deblur_debug_fft(int32_t n, int32_t batch, int32_t which, const float* in, f
         } else if (which == 3) {
             row_inv(&tmp, s, reinterpret_cast<const float2*>(in), out, 0);
         } else {
-            DISPATCH_N(&tmp, launch_col_fft_dbg, s, reinterpret_cast<const float2*>(in),
-                       reinterpret_cast<float2*>(out), which == 1 ? -1 : 1);
+            DISPATCH_NW(&tmp, tmp.plan.col_waves, launch_col_fft_dbg, s, reinterpret_cast<const float2*>(in),
+                        reinterpret_cast<float2*>(out), which == 1 ? -1 : 1);
         }
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(s);

@@ -51,11 +51,16 @@ struct SolveParams {
     int reg, bc, positivity, r;
 };
 
-template <int N> struct Cfg {
+// Waves per workgroup a frame kernel may use: the two shapes that split the
+// frame evenly (the smaller one doubles the workgroup count).
+template <int N> constexpr int waves_hi() { return N == 160 ? 2 : 4; }
+template <int N> constexpr int waves_lo() { return waves_hi<N>() / 2; }
+
+template <int N, int WV = waves_hi<N>()> struct Cfg {
     static constexpr int n = N / 2;          // complex length of a row transform
     static constexpr int LwR = kPts / n;     // rows per wave
     static constexpr int LwC = kPts / N;     // columns per wave
-    static constexpr int W = (N == 160) ? 2 : 4;   // waves per workgroup
+    static constexpr int W = WV;             // waves per workgroup
     static constexpr int NT = W * kLanes;
     static constexpr int RB = W * LwR;       // rows per row workgroup
     static constexpr int CB = W * LwC;       // columns per column workgroup
@@ -83,10 +88,10 @@ template <int N> struct Cfg {
 
 // Transposed store of the WG's rows (natural-order row FFTs of the packed
 // real rows, in sbuf) as packed half-spectra out[f][i0 + row].
-template <int N>
+template <int N, int WV>
 __device__ __forceinline__ void store_spectrum_T(const float2* __restrict__ sbuf, const float2* __restrict__ tw,
                                                  float2* __restrict__ out, int i0, int tid_in) {
-    using C = Cfg<N>;
+    using C = Cfg<N, WV>;
     constexpr int n = C::n;
     const int tid = fresh_lane(tid_in);
 #pragma unroll 4
@@ -111,10 +116,10 @@ __device__ __forceinline__ void store_spectrum_T(const float2* __restrict__ sbuf
 // Transposed load of packed half-spectra in[f][i0 + row] into sbuf[row][f].
 // All global loads of a thread are issued before any LDS store, so their
 // latencies overlap instead of being paid once per unrolled group.
-template <int N>
+template <int N, int WV>
 __device__ __forceinline__ void load_spectrum_T(float2* __restrict__ sbuf, const float2* __restrict__ in,
                                                 int i0, int tid) {
-    using C = Cfg<N>;
+    using C = Cfg<N, WV>;
     constexpr int n = C::n;
     constexpr int PER = C::RB * n / C::NT;
     static_assert(PER * C::NT == C::RB * n, "transpose does not divide the workgroup");
@@ -138,10 +143,10 @@ __device__ __forceinline__ void load_spectrum_T(float2* __restrict__ sbuf, const
 // sequence Z = E + i O whose inverse length-n FFT gives (x[2m], x[2m+1]):
 //   E = (X_f + conj X_{n-f}) / 2,  O = (X_f - conj X_{n-f}) W_N^{-f} / 2,
 // with X_0 = Re P_0 (DC) and X_{n} = Im P_0 (Nyquist) from the packed slot 0.
-template <int N>
+template <int N, int WV>
 __device__ __forceinline__ void load_c2r_T(float2* __restrict__ sbuf, const float2* __restrict__ in,
                                            const float2* __restrict__ tw, int i0, int tid_in) {
-    using C = Cfg<N>;
+    using C = Cfg<N, WV>;
     constexpr int n = C::n;
     const int tid = fresh_lane(tid_in);
     constexpr int PAIRS = C::RB * (n / 2 + 1);
@@ -243,9 +248,9 @@ __device__ __forceinline__ void row_fft_wave(float2 (&v)[kV], float2* __restrict
 }
 
 // Copies the column (COL) or row twiddle tables of frame N into LDS.
-template <int N, bool COL>
+template <int N, int WV, bool COL>
 __device__ __forceinline__ void load_twiddles(float2* __restrict__ tw, const float2* __restrict__ twg, int tid) {
-    using C = Cfg<N>;
+    using C = Cfg<N, WV>;
     constexpr int cnt = COL ? C::TWC : C::TWR;
     const float2* src = twg + (COL ? 0 : C::TWC);
     for (int e = tid; e < cnt; e += C::NT) tw[e] = src[e];
@@ -269,17 +274,17 @@ __global__ void k_make_twiddles(float2* __restrict__ twg) {
 
 // x (frames) -> packed row half-spectra of b_k . x for each mask k of the
 // tile (masked != 0) or of x itself (masked == 0, one output).
-template <int N>
-__global__ __launch_bounds__(Cfg<N>::NT) void k_row_fwd(const float* __restrict__ x, const TileInfo* __restrict__ tiles,
+template <int N, int WV>
+__global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_fwd(const float* __restrict__ x, const TileInfo* __restrict__ tiles,
                                                         const float* __restrict__ tentX, const float2* __restrict__ twg,
                                                         float2* __restrict__ out, int masked) {
-    using C = Cfg<N>;
+    using C = Cfg<N, WV>;
     constexpr int n = C::n;
     __shared__ float2 sbuf[C::RB * C::LSR + kLinePad];
     __shared__ float2 tw[C::TWR];
     const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    load_twiddles<N, false>(tw, twg, tid);
+    load_twiddles<N, WV, false>(tw, twg, tid);
     const TileInfo ti = tiles[t];
     const int nk = masked ? ti.nkx : 1;
     const int kstride = masked ? kMaxK : 1;
@@ -305,24 +310,24 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_fwd(const float* __restrict_
         }
         row_fft_wave<N>(v, sw, tw, lane);
         __syncthreads();
-        store_spectrum_T<N>(sbuf, tw, out + ((size_t)t * kstride + k) * C::SPEC, i0, tid);
+        store_spectrum_T<N, WV>(sbuf, tw, out + ((size_t)t * kstride + k) * C::SPEC, i0, tid);
         __syncthreads();
     }
 }
 
 // Packed row half-spectra -> real frames: out = sum_k b_k . C2R(in_k)
 // (masked != 0) or C2R(in_0) (masked == 0).
-template <int N>
-__global__ __launch_bounds__(Cfg<N>::NT) void k_row_inv(const float2* __restrict__ in, const TileInfo* __restrict__ tiles,
+template <int N, int WV>
+__global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_inv(const float2* __restrict__ in, const TileInfo* __restrict__ tiles,
                                                         const float* __restrict__ tentX, const float2* __restrict__ twg,
                                                         float* __restrict__ out, int masked) {
-    using C = Cfg<N>;
+    using C = Cfg<N, WV>;
     constexpr int n = C::n;
     __shared__ float2 sbuf[C::RB * C::LSR + kLinePad];
     __shared__ float2 tw[C::TWR];
     const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    load_twiddles<N, false>(tw, twg, tid);
+    load_twiddles<N, WV, false>(tw, twg, tid);
     const TileInfo ti = tiles[t];
     const int nk = masked ? ti.nkx : 1;
     const int kstride = masked ? kMaxK : 1;
@@ -332,7 +337,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_inv(const float2* __restrict
     for (int s = 0; s < kV; ++s) acc[s] = make_float2(0.f, 0.f);
     for (int k = 0; k < nk; ++k) {
         __syncthreads();
-        load_c2r_T<N>(sbuf, in + ((size_t)t * kstride + k) * C::SPEC, tw, i0, tid);
+        load_c2r_T<N, WV>(sbuf, in + ((size_t)t * kstride + k) * C::SPEC, tw, i0, tid);
         __syncthreads();
         float2 v[kV];
         row_c2r_ready<N>(v, sw, tw, lane);
@@ -363,21 +368,32 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_inv(const float2* __restrict
 // Column kernels
 // ---------------------------------------------------------------------------
 
-// Work items of the column kernels.  Item I < n_tiles * n_cg is column group
-// cg = I / n_tiles of tile t = I mod n_tiles (column-group-major).  The packed
-// column 0 of a half-plane carries two real columns, DC (real part) and
-// Nyquist (imaginary part); the wave owning column 0 treats it as the DC
-// column, and n_nyq = ceil(n_tiles / W) extra items give every tile one wave
-// for its Nyquist column (wave w of extra item j serves tile j W + w).  Both
-// are then ordinary complex columns multiplied by their own spectrum column
-// (0 or N/2), so no wave needs the g -> -g exchange of the packed form.
+// Work items of the column kernels.  Item I < n_tiles * n_cg is one column
+// group of one tile; the packed column 0 of a half-plane carries two real
+// columns, DC (real part) and Nyquist (imaginary part): the wave owning
+// column 0 treats it as the DC column, and n_nyq = ceil(n_tiles / W) extra
+// items give every tile one wave for its Nyquist column (wave w of extra
+// item j serves tile j W + w).  Both are then ordinary complex columns
+// multiplied by their own spectrum column (0 or N/2), so no wave needs the
+// g -> -g exchange of the packed form.
 //
 // XCD-aware mapping: workgroups go to the 8 XCDs round-robin by linear id,
-// so workgroup L runs on XCD L mod 8.  Item I = (L mod 8) * per + L / 8 gives
-// every XCD a contiguous range of items: an XCD then works on one or two
-// column groups of all tiles, and that column block of every PSF spectrum
-// (CB columns x N x 8 bytes per node) is shared in its L2 by the up-to-9
-// tiles that use it.
+// so workgroup L runs on XCD L mod 8, and item I = (L mod 8) * per + L / 8
+// gives every XCD a contiguous range of items.  The tile order decides what
+// that range holds:
+//   kOrderColumnMajor  items column-group-major: an XCD works on one or two
+//                      column groups of all tiles, and that column block of
+//                      every PSF spectrum is shared in its L2 by the up-to-9
+//                      tiles that use it;
+//   kOrderTileMajor    items tile-major: an XCD holds whole tiles, so the
+//                      tile's half-planes stay in one L2;
+//   kOrderHeavyFirst   column-group-major over the tiles sorted by their
+//                      number of PSF terms, most first (perm), so the longest
+//                      items start first.
+// perm maps the position of a tile in the order to the tile (identity for
+// the first two orders).
+enum { kOrderColumnMajor = 0, kOrderTileMajor = 1, kOrderHeavyFirst = 2 };
+
 struct ColItem {
     int t;        // tile of this wave
     int f0;       // first packed column of this wave (0 for a Nyquist wave)
@@ -385,9 +401,9 @@ struct ColItem {
     bool valid;   // false: padding workgroup or Nyquist slot beyond the last tile
 };
 
-template <int N>
-__device__ __forceinline__ ColItem col_item(int n_tiles, int wave) {
-    using C = Cfg<N>;
+template <int N, int WV>
+__device__ __forceinline__ ColItem col_item(int n_tiles, const int* __restrict__ perm, int order, int wave) {
+    using C = Cfg<N, WV>;
     const int main_items = n_tiles * C::CG;
     const int items = main_items + (n_tiles + C::W - 1) / C::W;
     const int per = (items + 7) / 8;
@@ -395,23 +411,31 @@ __device__ __forceinline__ ColItem col_item(int n_tiles, int wave) {
     const int I = (L % 8) * per + L / 8;
     ColItem it;
     if (I < main_items) {
-        const int cg = I / n_tiles;
-        it.t = I - cg * n_tiles;
+        int cg, pos;
+        if (order == kOrderTileMajor) {
+            pos = I / C::CG;
+            cg = I - pos * C::CG;
+        } else {
+            cg = I / n_tiles;
+            pos = I - cg * n_tiles;
+        }
+        it.t = perm[pos];
         it.f0 = cg * C::CB + wave * C::LwC;
         it.nyq = false;
         it.valid = true;
     } else {
-        it.t = (I - main_items) * C::W + wave;
+        const int pos = (I - main_items) * C::W + wave;
+        it.valid = I < items && pos < n_tiles;
+        it.t = it.valid ? perm[pos] : 0;
         it.f0 = 0;
         it.nyq = true;
-        it.valid = I < items && it.t < n_tiles;
     }
     return it;
 }
 
-template <int N>
+template <int N, int WV>
 constexpr int col_grid(int n_tiles) {
-    using C = Cfg<N>;
+    using C = Cfg<N, WV>;
     const int items = n_tiles * C::CG + (n_tiles + C::W - 1) / C::W;
     return 8 * ((items + 7) / 8);
 }
@@ -439,7 +463,7 @@ __device__ __forceinline__ void col_out(float2* __restrict__ p, float2 v, int mo
 // Loads the spectrum values of one term for the wave's columns, in the
 // forward transform's output layout: column f0 + line, or column N/2 on
 // every line of a Nyquist wave.
-template <int N>
+template <int N, int WV>
 __device__ __forceinline__ void load_spec(float2 (&sp)[kV], const float2* __restrict__ base, const ColItem& it,
                                           int lane) {
     constexpr int RL = last_radix<N, kFwd>();
@@ -453,18 +477,18 @@ __device__ __forceinline__ void load_spec(float2 (&sp)[kV], const float2* __rest
 }
 
 // H: Yc[f][:] = IFFT_col( sum_{ky,kx} spec_k . FFT_col(a_ky . Z_kx[f][:]) )
-template <int N>
-__global__ __launch_bounds__(Cfg<N>::NT) void k_col_H(const float2* __restrict__ Zk, const TileInfo* __restrict__ tiles,
+template <int N, int WV>
+__global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_H(const float2* __restrict__ Zk, const TileInfo* __restrict__ tiles,
                                                       const float* __restrict__ tentY, const float2* __restrict__ spec,
                                                       const float2* __restrict__ twg, float2* __restrict__ Yc,
-                                                      int n_tiles) {
-    using C = Cfg<N>;
+                                                      int n_tiles, const int* __restrict__ perm, int order) {
+    using C = Cfg<N, WV>;
     constexpr int LPL = lanes_per_line<N>();
     __shared__ float2 lds[C::W * (C::LwC * C::LSC + kLinePad)];
     __shared__ float2 tw[C::TWC];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const ColItem it = col_item<N>(n_tiles, wave);
-    load_twiddles<N, true>(tw, twg, tid);
+    const ColItem it = col_item<N, WV>(n_tiles, perm, order, wave);
+    load_twiddles<N, WV, true>(tw, twg, tid);
     __syncthreads();
     if (!it.valid) return;
     const int t = it.t, line = lane / LPL, mode = col_mode(it, line);
@@ -492,7 +516,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_H(const float2* __restrict__
             }
         }
         fft_passes<N, kFwd>(v, sw, tw, lane);
-        load_spec<N>(sp, spec + (size_t)tp->spec[ky * kMaxK + kx] * C::NSPEC, it, fresh_lane(lane));
+        load_spec<N, WV>(sp, spec + (size_t)tp->spec[ky * kMaxK + kx] * C::NSPEC, it, fresh_lane(lane));
 #pragma unroll
         for (int s = 0; s < kV; ++s) acc[s] = cadd(acc[s], cmul(sp[s], v[s]));
     }
@@ -507,18 +531,18 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_H(const float2* __restrict__
 }
 
 // H^T: Gk[kx][f][:] = sum_ky a_ky . IFFT_col( conj(spec_k) . FFT_col(Rr[f][:]) )
-template <int N>
-__global__ __launch_bounds__(Cfg<N>::NT) void k_col_Ht(const float2* __restrict__ Rr, const TileInfo* __restrict__ tiles,
+template <int N, int WV>
+__global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_Ht(const float2* __restrict__ Rr, const TileInfo* __restrict__ tiles,
                                                        const float* __restrict__ tentY, const float2* __restrict__ spec,
                                                        const float2* __restrict__ twg, float2* __restrict__ Gk,
-                                                       int n_tiles) {
-    using C = Cfg<N>;
+                                                       int n_tiles, const int* __restrict__ perm, int order) {
+    using C = Cfg<N, WV>;
     constexpr int LPL = lanes_per_line<N>();
     __shared__ float2 lds[C::W * (C::LwC * C::LSC + kLinePad)];
     __shared__ float2 tw[C::TWC];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const ColItem it = col_item<N>(n_tiles, wave);
-    load_twiddles<N, true>(tw, twg, tid);
+    const ColItem it = col_item<N, WV>(n_tiles, perm, order, wave);
+    load_twiddles<N, WV, true>(tw, twg, tid);
     __syncthreads();
     if (!it.valid) return;
     const int t = it.t, line = lane / LPL, mode = col_mode(it, line);
@@ -544,24 +568,28 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_Ht(const float2* __restrict_
 #pragma unroll
             for (int s = 0; s < kV; ++s) acc[s] = make_float2(0.f, 0.f);
         }
-        load_spec<N>(sp, spec + (size_t)tp->spec[ky * kMaxK + kx] * C::NSPEC, it, fresh_lane(lane));
+        load_spec<N, WV>(sp, spec + (size_t)tp->spec[ky * kMaxK + kx] * C::NSPEC, it, fresh_lane(lane));
         float2 v[kV];
 #pragma unroll
         for (int s = 0; s < kV; ++s) v[s] = cmulc(S[s], sp[s]);
         fft_passes<N, kInv>(v, sw, tw + C::TWC_F, lane);
         const float* am = tentY + ((size_t)ty * kMaxK + ky) * N;
-#pragma unroll
-        for (int s = 0; s < kV; ++s) {
-            int q, g;
-            slot_pos<N, 5>(lane, s, q, g);
-            acc[s] = cadd(acc[s], cscale(v[s], am[g]));
-        }
-        if (ky == nky - 1) {
-            float2* gt = Gk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)it.f0 * N;
+        {
+            const int ln = fresh_lane(lane);
 #pragma unroll
             for (int s = 0; s < kV; ++s) {
                 int q, g;
-                slot_pos<N, 5>(lane, s, q, g);
+                slot_pos<N, 5>(ln, s, q, g);
+                acc[s] = cadd(acc[s], cscale(v[s], am[g]));
+            }
+        }
+        if (ky == nky - 1) {
+            float2* gt = Gk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)it.f0 * N;
+            const int ln = fresh_lane(lane);
+#pragma unroll
+            for (int s = 0; s < kV; ++s) {
+                int q, g;
+                slot_pos<N, 5>(ln, s, q, g);
                 col_out(gt + q * ls + g, acc[s], mode, q);
             }
         }
@@ -570,16 +598,16 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_Ht(const float2* __restrict_
 
 // Diagnostic: forward (dir < 0) or unnormalised inverse (dir > 0) FFT of every
 // column in[t][f][:] of packed half-planes.
-template <int N>
-__global__ __launch_bounds__(Cfg<N>::NT) void k_col_fft_dbg(const float2* __restrict__ in, const float2* __restrict__ twg,
+template <int N, int WV>
+__global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_fft_dbg(const float2* __restrict__ in, const float2* __restrict__ twg,
                                                             float2* __restrict__ out, int dir) {
-    using C = Cfg<N>;
+    using C = Cfg<N, WV>;
     __shared__ float2 lds[C::W * (C::LwC * C::LSC + kLinePad)];
     __shared__ float2 tw[C::TWC];
     const int t = blockIdx.y;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int f0 = blockIdx.x * C::CB + wave * C::LwC;
-    load_twiddles<N, true>(tw, twg, tid);
+    load_twiddles<N, WV, true>(tw, twg, tid);
     __syncthreads();
     float2* sw = lds + wave * (C::LwC * C::LSC + kLinePad);
     const float2* it = in + (size_t)t * C::SPEC + (size_t)f0 * N;
@@ -620,9 +648,9 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_col_fft_dbg(const float2* __rest
 // Fused row kernels of the Local-Solver step
 // ---------------------------------------------------------------------------
 
-template <int N>
+template <int N, int WV>
 __device__ __forceinline__ float block_sum(float v, float* red, int tid) {
-    using C = Cfg<N>;
+    using C = Cfg<N, WV>;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     if ((tid & 63) == 0) red[tid >> 6] = v;
@@ -636,20 +664,20 @@ __device__ __forceinline__ float block_sum(float v, float* red, int tid) {
 
 // H x (from Yc) -> residual W (H x - y) on the block -> its packed row spectra.
 // obj_part[t * RG + rg] = 1/2 sum W (H x - y)^2 over the workgroup's rows.
-template <int N>
-__global__ __launch_bounds__(Cfg<N>::NT) void k_row_resid(const float2* __restrict__ Yc, const float2* __restrict__ yw,
+template <int N, int WV>
+__global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_resid(const float2* __restrict__ Yc, const float2* __restrict__ yw,
                                                           const float2* __restrict__ twg, float2* __restrict__ Rr,
                                                           float* __restrict__ obj_part) {
-    using C = Cfg<N>;
+    using C = Cfg<N, WV>;
     constexpr int n = C::n;
     __shared__ float2 sbuf[C::RB * C::LSR + kLinePad];
     __shared__ float2 tw[C::TWR];
     __shared__ float red[C::W];
     const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    load_twiddles<N, false>(tw, twg, tid);
+    load_twiddles<N, WV, false>(tw, twg, tid);
     __syncthreads();
-    load_c2r_T<N>(sbuf, Yc + (size_t)t * C::SPEC, tw, i0, tid);
+    load_c2r_T<N, WV>(sbuf, Yc + (size_t)t * C::SPEC, tw, i0, tid);
     __syncthreads();
     float2* sw = sbuf + line_off<C::n>(wave * C::LwR);
     float2 v[kV];
@@ -670,8 +698,8 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_resid(const float2* __restri
     wave_sync();
     row_fft_wave<N>(v, sw, tw, lane);
     __syncthreads();
-    store_spectrum_T<N>(sbuf, tw, Rr + (size_t)t * C::SPEC, i0, tid);
-    const float tot = block_sum<N>(obj, red, tid);
+    store_spectrum_T<N, WV>(sbuf, tw, Rr + (size_t)t * C::SPEC, i0, tid);
+    const float tot = block_sum<N, WV>(obj, red, tid);
     if (tid == 0) obj_part[t * C::RG + blockIdx.x] = 0.5f * tot;
 }
 
@@ -700,13 +728,13 @@ constexpr int kSeg = 8;
 //          two regulariser scales; writes the new x to HBM and to LDS.
 // Phase 3: each wave reads its rows of the new x from LDS and, per mask k,
 //          does the forward row FFT and the transposed store of Z_k.
-template <int N>
-__global__ __launch_bounds__(Cfg<N>::NT) void k_row_update(
+template <int N, int WV>
+__global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
         const float2* __restrict__ Gk, const float* __restrict__ xc, const float* __restrict__ u,
         const TileInfo* __restrict__ tiles, const float* __restrict__ tentX, const float* __restrict__ omY,
         const float* __restrict__ omX, const float* __restrict__ tau, SolveParams P,
         const float2* __restrict__ twg, float* __restrict__ xn, float2* __restrict__ Zk) {
-    using C = Cfg<N>;
+    using C = Cfg<N, WV>;
     constexpr int n = C::n;
     static_assert(C::RB * N * sizeof(float) <= C::RB * C::LSR * sizeof(float2), "LDS view too small");
     static_assert((N * (C::RB / kSeg)) % C::NT == 0, "update tasks do not divide the workgroup");
@@ -715,7 +743,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_update(
     float* sg = reinterpret_cast<float*>(sbuf);   // [RB][N] natural view
     const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    load_twiddles<N, false>(tw, twg, tid);
+    load_twiddles<N, WV, false>(tw, twg, tid);
     const TileInfo ti = tiles[t];
     float2* sw = sbuf + line_off<C::n>(wave * C::LwR);
 
@@ -726,7 +754,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_update(
         for (int s = 0; s < kV; ++s) gd[s] = make_float2(0.f, 0.f);
         for (int kx = 0; kx < ti.nkx; ++kx) {
             __syncthreads();
-            load_c2r_T<N>(sbuf, Gk + ((size_t)t * kMaxK + kx) * C::SPEC, tw, i0, tid);
+            load_c2r_T<N, WV>(sbuf, Gk + ((size_t)t * kMaxK + kx) * C::SPEC, tw, i0, tid);
             __syncthreads();
             float2 v[kV];
             row_c2r_ready<N>(v, sw, tw, lane);
@@ -857,7 +885,7 @@ __global__ __launch_bounds__(Cfg<N>::NT) void k_row_update(
         __syncthreads();
         row_fft_wave<N>(v, sw, tw, lane);
         __syncthreads();
-        store_spectrum_T<N>(sbuf, tw, Zk + ((size_t)t * kMaxK + kx) * C::SPEC, i0, tid);
+        store_spectrum_T<N, WV>(sbuf, tw, Zk + ((size_t)t * kMaxK + kx) * C::SPEC, i0, tid);
     }
 }
 

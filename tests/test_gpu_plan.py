@@ -1,0 +1,108 @@
+"""Launch plans and the autotuner: every plan gives the same iterates."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import operator as op
+from oracle.layout import make_layout
+from oracle.solver import Problem
+
+pytestmark = pytest.mark.gpu
+
+# (M, T, pitch, overlap, P, G): supports 158, 318 and 638 -> frames 160, 320, 640
+GEOMETRIES = {160: (256, 2, 128, 16, 15, 2), 320: (512, 2, 256, 32, 31, 2), 640: (1024, 2, 512, 64, 63, 2)}
+
+
+def _problem(frame, seed=0):
+    M, T, p, o, P, G = GEOMETRIES[frame]
+    L = make_layout(M, T, p, o, P, G)
+    rng = np.random.default_rng(seed)
+    psfs = rng.random((G, G, P, P)) ** 4
+    psfs /= psfs.sum(axis=(2, 3), keepdims=True)
+    y = rng.random((M, M))
+    W = 0.5 + rng.random((M, M))
+    return Problem(L, psfs, y, W, lam=1e-3, reg_param=1e-2, gamma=0.5, rho=1.0, operator=object())
+
+
+def _waves(frame):
+    return (1, 2) if frame == 160 else (2, 4)
+
+
+def _run(ctx, x0, u0, rounds=2, n_inner=3):
+    from tests._gpu import to_dev
+    ctx.set_state(to_dev(x0), to_dev(u0))
+    res = ctx.run(rounds, n_inner)
+    x, u = ctx.get_state()
+    return x.cpu().numpy(), u.cpu().numpy(), res
+
+
+@pytest.mark.parametrize("frame", [160, 320, 640])
+def test_iterates_identical_under_every_plan(frame):
+    from tests._gpu import context_of
+    prob = _problem(frame)
+    ctx = context_of(prob)
+    assert ctx.tiles[0].frame == frame
+    pl0 = ctx.plan()
+    assert (pl0.frame, pl0.col_waves, pl0.row_waves, pl0.tile_order) == (frame, _waves(frame)[1],
+                                                                         _waves(frame)[1], 0)
+    rng = np.random.default_rng(1)
+    x0 = rng.random(ctx.support_total).astype(np.float32)
+    u0 = rng.random(ctx.support_total).astype(np.float32)
+    xr, ur, rr = _run(ctx, x0, u0)
+    objs = []
+    for cw, rw, order in itertools.product(_waves(frame), _waves(frame), (0, 1, 2)):
+        ctx.set_plan(col_waves=cw, row_waves=rw, tile_order=order)
+        x, u, res = _run(ctx, x0, u0)
+        assert np.array_equal(x, xr), (cw, rw, order)
+        assert np.array_equal(u, ur), (cw, rw, order)
+        assert res == rr
+        objs.append(sum(ctx.objective()))
+    # only the grouping of the objective's partial sums follows the plan
+    assert (max(objs) - min(objs)) <= 1e-6 * abs(objs[0])
+    ctx.close()
+
+
+def test_set_plan_rejects_bad_plans():
+    from paper_1705_06603_amd import _lib as dl
+    from tests._gpu import context_of
+    ctx = context_of(_problem(320))
+    for bad in ({"frame": 640}, {"col_waves": 1}, {"row_waves": 3}, {"tile_order": 3}, {"tile_order": -1}):
+        with pytest.raises(dl.DeblurError) as e:
+            ctx.set_plan(**bad)
+        assert e.value.code == -1, bad
+    pl = ctx.plan()
+    assert (pl.col_waves, pl.row_waves, pl.tile_order) == (4, 4, 0)   # unchanged by the rejected calls
+    ctx.close()
+
+
+def test_autotune_picks_the_fastest_measured_plan():
+    from paper_1705_06603_amd import _lib as dl
+    from tests._gpu import params_of, context_of
+    prob = _problem(320)
+    best, trials = dl.autotune(params_of(prob), prob.psfs, n_inner=3, reps=2)
+    # frames 320 and 640 hold the 318-px supports: 12 plans each
+    assert sorted({t.frame for t in trials}) == [320, 640]
+    assert len(trials) == 24
+    assert all(t.us_per_iter > 0 for t in trials)
+    assert best.us_per_iter == min(t.us_per_iter for t in trials)
+    # the chosen plan runs and gives the default plan's iterates at its frame
+    ctx_a = context_of(prob, fft_size=best.frame)
+    ctx_b = context_of(prob, fft_size=best.frame)
+    ctx_b.set_plan(best)
+    rng = np.random.default_rng(2)
+    x0 = rng.random(ctx_a.support_total).astype(np.float32)
+    xa, _, _ = _run(ctx_a, x0, x0)
+    xb, _, _ = _run(ctx_b, x0, x0)
+    assert np.array_equal(xa, xb)
+    ctx_a.close()
+    ctx_b.close()
+
+
+def test_autotune_respects_a_fixed_frame():
+    from paper_1705_06603_amd import _lib as dl
+    from tests._gpu import params_of
+    prob = _problem(160)
+    best, trials = dl.autotune(params_of(prob, fft_size=320), prob.psfs, n_inner=2, reps=1)
+    assert {t.frame for t in trials} == {320} and len(trials) == 12
+    assert best.frame == 320
