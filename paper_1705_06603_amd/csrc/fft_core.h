@@ -2,8 +2,10 @@
 //
 // One wavefront owns kPts = 1280 complex points: kV = 20 values per lane, so
 // it transforms 1280 / n lines of length n at once.  A transform is a chain
-// of radix-R passes (R in {5, 4, 2}; 20 is a multiple of each, so every lane
-// does 20/R butterflies per pass and no lane idles).  Between passes the
+// of radix-R passes (R in {20, 5, 4, 2}; each divides 20, so every lane does
+// 20/R butterflies per pass and no lane idles).  A radix-20 pass is one
+// length-20 DFT per lane done in registers (4 x 5 with constant twiddles),
+// which saves one LDS exchange over separate radix-5 and radix-4 passes.  Between passes the
 // values go through the wave's private LDS region; waves never wait on each
 // other, only on their own LDS traffic (wave_sync).
 //
@@ -19,8 +21,8 @@
 // Register layout "L_R" (the input layout of a radix-R first pass, which is
 // also the output layout of a radix-R last pass): lane l, slot b*R + r holds
 // element j + r n/R of line q.  LDS and global addresses of a lane are one
-// per-lane base plus compile-time offsets.  The forward plan starts with radix 5 and the inverse
-// plan is the forward plan reversed, so a forward transform's output layout
+// per-lane base plus compile-time offsets.  The forward plan starts with
+// radix 20 and the inverse plan is the forward plan reversed, so a forward transform's output layout
 // is the inverse transform's input layout and vice versa: a spectrum can be
 // multiplied and transformed back without touching LDS.
 #pragma once
@@ -97,19 +99,54 @@ __device__ __forceinline__ void dft5(float2* v) {
     v[3] = csub(b2, id2);
 }
 
+// Length-20 DFT in registers, as 4 x 5 (Cooley-Tukey with constant
+// twiddles): input index r = 5a + b, output index k = c + 4d, so
+//   y[c + 4d] = sum_b w5^{bd} w20^{bc} sum_a x[5a + b] w4^{ac},
+// with w_m = exp(DIR 2 pi i / m): five length-4 DFTs, twiddles w20^{bc},
+// four length-5 DFTs.
+template <int DIR>
+__device__ __forceinline__ void dft20(float2* v) {
+    // cos and sin of 2 pi m / 20 for the products m = b c (b < 5, c < 4)
+    constexpr float kC[13] = {1.f, 0.95105651629515357f, 0.80901699437494742f, 0.58778525229247313f,
+                              0.30901699437494742f, 0.f, -0.30901699437494742f, 0.f, -0.80901699437494742f,
+                              -0.95105651629515357f, 0.f, 0.f, -0.80901699437494742f};
+    constexpr float kS[13] = {0.f, 0.30901699437494742f, 0.58778525229247313f, 0.80901699437494742f,
+                              0.95105651629515357f, 1.f, 0.95105651629515357f, 0.f, 0.58778525229247313f,
+                              0.30901699437494742f, 0.f, 0.f, -0.58778525229247313f};
+    float2 T[5][4];
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+        float2 u[4] = {v[b], v[5 + b], v[10 + b], v[15 + b]};
+        dft4<DIR>(u);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int m = b * c;
+            T[b][c] = (m == 0) ? u[c] : cmul(u[c], make_float2(kC[m], DIR * kS[m]));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        float2 w[5] = {T[0][c], T[1][c], T[2][c], T[3][c], T[4][c]};
+        dft5<DIR>(w);
+#pragma unroll
+        for (int d = 0; d < 5; ++d) v[c + 4 * d] = w[d];
+    }
+}
+
 template <int R, int DIR>
 __device__ __forceinline__ void dft(float2* v) {
     if constexpr (R == 2) dft2<DIR>(v);
     else if constexpr (R == 4) dft4<DIR>(v);
-    else dft5<DIR>(v);
+    else if constexpr (R == 5) dft5<DIR>(v);
+    else dft20<DIR>(v);
 }
 
 // Forward radix plans; the inverse runs them in reverse order.
 template <int n> struct Plan;
-template <> struct Plan<80>  { static constexpr int np = 3; static constexpr int r[5] = {5, 4, 4, 0, 0}; };
-template <> struct Plan<160> { static constexpr int np = 4; static constexpr int r[5] = {5, 4, 4, 2, 0}; };
-template <> struct Plan<320> { static constexpr int np = 4; static constexpr int r[5] = {5, 4, 4, 4, 0}; };
-template <> struct Plan<640> { static constexpr int np = 5; static constexpr int r[5] = {5, 4, 4, 4, 2}; };
+template <> struct Plan<80>  { static constexpr int np = 2; static constexpr int r[5] = {20, 4, 0, 0, 0}; };
+template <> struct Plan<160> { static constexpr int np = 3; static constexpr int r[5] = {20, 4, 2, 0, 0}; };
+template <> struct Plan<320> { static constexpr int np = 3; static constexpr int r[5] = {20, 4, 4, 0, 0}; };
+template <> struct Plan<640> { static constexpr int np = 4; static constexpr int r[5] = {20, 4, 4, 2, 0}; };
 
 template <int n, int DIR, int p>
 constexpr int pass_radix() {
@@ -118,6 +155,13 @@ constexpr int pass_radix() {
 // Radix of the first / last pass of a transform.
 template <int n, int DIR> constexpr int first_radix() { return pass_radix<n, DIR, 0>(); }
 template <int n, int DIR> constexpr int last_radix() { return pass_radix<n, DIR, Plan<n>::np - 1>(); }
+// Layout of a transform's natural-order side: the forward transform's input
+// and the inverse transform's output (the inverse plan is the forward plan
+// reversed, so both are L_R of the forward plan's first radix).
+template <int n> constexpr int nat_radix() {
+    static_assert(first_radix<n, kFwd>() == last_radix<n, kInv>(), "plan is not reversible");
+    return first_radix<n, kFwd>();
+}
 
 // Line stride (in float2) of the LDS exchange buffers.  It is odd, so the
 // column-wise (transposed) accesses of 16 consecutive lines hit distinct

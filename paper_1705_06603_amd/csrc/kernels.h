@@ -293,7 +293,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_fwd(const float* __res
 #pragma unroll
     for (int s = 0; s < kV; ++s) {
         int q, m;
-        slot_pos<n, 5>(lane, s, q, m);
+        slot_pos<n, nat_radix<n>()>(lane, s, q, m);
         const int row = i0 + wave * C::LwR + q;
         xv[s] = *reinterpret_cast<const float2*>(xt + (size_t)row * N + 2 * m);
     }
@@ -305,7 +305,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_fwd(const float* __res
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
             int q, m;
-            slot_pos<n, 5>(lane, s, q, m);
+            slot_pos<n, nat_radix<n>()>(lane, s, q, m);
             v[s] = masked ? make_float2(bm[2 * m] * xv[s].x, bm[2 * m + 1] * xv[s].y) : xv[s];
         }
         row_fft_wave<N>(v, sw, tw, lane);
@@ -345,7 +345,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_inv(const float2* __re
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
             int q, m;
-            slot_pos<n, 5>(lane, s, q, m);
+            slot_pos<n, nat_radix<n>()>(lane, s, q, m);
             if (masked) {
                 acc[s].x += bm[2 * m] * v[s].x;
                 acc[s].y += bm[2 * m + 1] * v[s].y;
@@ -358,7 +358,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_inv(const float2* __re
 #pragma unroll
     for (int s = 0; s < kV; ++s) {
         int q, m;
-        slot_pos<n, 5>(lane, s, q, m);
+        slot_pos<n, nat_radix<n>()>(lane, s, q, m);
         const int row = i0 + wave * C::LwR + q;
         *reinterpret_cast<float2*>(ot + (size_t)row * N + 2 * m) = acc[s];
     }
@@ -511,7 +511,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_H(const float2* __rest
 #pragma unroll
             for (int s = 0; s < kV; ++s) {
                 int q, g;
-                slot_pos<N, 5>(ln, s, q, g);
+                slot_pos<N, nat_radix<N>()>(ln, s, q, g);
                 v[s] = cscale(col_in(zt[q * ls + g], mode), am[g]);
             }
         }
@@ -525,7 +525,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_H(const float2* __rest
 #pragma unroll
     for (int s = 0; s < kV; ++s) {
         int q, g;
-        slot_pos<N, 5>(lane, s, q, g);
+        slot_pos<N, nat_radix<N>()>(lane, s, q, g);
         col_out(yt + q * ls + g, acc[s], mode, q);
     }
 }
@@ -557,7 +557,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_Ht(const float2* __res
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
             int q, g;
-            slot_pos<N, 5>(lane, s, q, g);
+            slot_pos<N, nat_radix<N>()>(lane, s, q, g);
             S[s] = col_in(rt[q * ls + g], mode);
         }
     }
@@ -579,7 +579,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_Ht(const float2* __res
 #pragma unroll
             for (int s = 0; s < kV; ++s) {
                 int q, g;
-                slot_pos<N, 5>(ln, s, q, g);
+                slot_pos<N, nat_radix<N>()>(ln, s, q, g);
                 acc[s] = cadd(acc[s], cscale(v[s], am[g]));
             }
         }
@@ -589,7 +589,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_Ht(const float2* __res
 #pragma unroll
             for (int s = 0; s < kV; ++s) {
                 int q, g;
-                slot_pos<N, 5>(ln, s, q, g);
+                slot_pos<N, nat_radix<N>()>(ln, s, q, g);
                 col_out(gt + q * ls + g, acc[s], mode, q);
             }
         }
@@ -687,7 +687,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_resid(const float2* __
 #pragma unroll
     for (int s = 0; s < kV; ++s) {
         int q, m;
-        slot_pos<n, 5>(lane, s, q, m);
+        slot_pos<n, nat_radix<n>()>(lane, s, q, m);
         const int row = i0 + wave * C::LwR + q;
         const float4 o = ywt[((size_t)row * N + 2 * m) >> 1];   // (y0, W0, y1, W1)
         const float d0 = v[s].x - o.x, d1 = v[s].y - o.z;
@@ -762,7 +762,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
 #pragma unroll
             for (int s = 0; s < kV; ++s) {
                 int q, m;
-                slot_pos<n, 5>(lane, s, q, m);
+                slot_pos<n, nat_radix<n>()>(lane, s, q, m);
                 const float2 b = *reinterpret_cast<const float2*>(bm + 2 * m);
                 gd[s].x += b.x * v[s].x;
                 gd[s].y += b.y * v[s].y;
@@ -772,7 +772,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
             int q, m;
-            slot_pos<n, 5>(lane, s, q, m);
+            slot_pos<n, nat_radix<n>()>(lane, s, q, m);
             *reinterpret_cast<float2*>(sg + (wave * C::LwR + q) * N + 2 * m) = gd[s];
         }
         __syncthreads();
@@ -877,7 +877,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
             int q, m;
-            slot_pos<n, 5>(ln, s, q, m);
+            slot_pos<n, nat_radix<n>()>(ln, s, q, m);
             const float2 b = *reinterpret_cast<const float2*>(bm + 2 * m);
             const float2 xv = *reinterpret_cast<const float2*>(xw + (wave * C::LwR + q) * N + 2 * m);
             v[s] = make_float2(b.x * xv.x, b.y * xv.y);
