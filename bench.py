@@ -38,9 +38,33 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def build_workload(tune=True):
-    """Scene, PSFs and the noisy observation of the batched workload, on a
-    context whose launch plan comes from the library's autotuner.
+WORKLOAD_TEXT = {
+    "batched": "batched: 2048x2048 image, 8x8 tiles (32-px overlap, uneven edge tiles), 8x8 grid of 31x31 "
+               "Moffat PSFs, Poisson+read noise, smoothed TV + positivity, 200 iterations (20 D-R rounds x 10 "
+               "Local-Solver steps), one solve per step",
+    "large": "large: 8192x8192 image, 16x16 tiles of 512-576 px (64-px overlap), 16x16 grid of 63x63 Moffat "
+             "PSFs with field-dependent FWHM and rotation, Poisson+read noise, smoothed TV + positivity, 300 "
+             "iterations (30 D-R rounds x 10 Local-Solver steps), one solve per step",
+    "combined": "combined: 16384x16384 image, 32x32 tiles (64-px overlap), 32x32 grid of 63x63 Moffat PSFs, "
+                "Poisson+read noise, smoothed TV + positivity, 300 iterations (30 D-R rounds x 10 "
+                "Local-Solver steps), one solve per step",
+}
+
+
+def parse_plan(text):
+    """'frame,col_waves,row_waves,order' with order a name or number."""
+    from paper_1705_06603_amd import _lib as dl
+    f, cw, rw, order = text.split(",")
+    names = {v: k for k, v in dl.ORDER_NAMES.items()}
+    pl = dl.Plan()
+    pl.frame, pl.col_waves, pl.row_waves = int(f), int(cw), int(rw)
+    pl.tile_order = names[order] if order in names else int(order)
+    return pl
+
+
+def build_workload(name="batched", tune=True, plan=None):
+    """Scene, PSFs and the noisy observation of a workload, on a context whose
+    launch plan comes from the library's autotuner (or is given).
 
     The blur is applied by the HIP library itself (deblur_blur_global);
     noise and weights come from the seeded generators."""
@@ -48,21 +72,23 @@ def build_workload(tune=True):
     from paper_1705_06603_amd import _lib as dl
     from paper_1705_06603_amd import workloads
 
-    w = workloads.WORKLOADS["batched"]
+    w = workloads.WORKLOADS[name]
     scene, psfs = workloads.make_workload(w)
     params = dl.make_params(w.M, w.tiles, w.pitch, w.overlap, w.grid, w.psf_size,
                             lam=w.lam, reg_param=w.eps, gamma=w.gamma, rho=w.rho)
     trials = []
-    plan = None
-    if tune:
-        plan, trials = dl.autotune(params, psfs, n_inner=w.n_inner, reps=3)
+    if plan is None and tune:
+        plan, trials = dl.autotune(params, psfs, n_inner=w.n_inner, reps=5)
+    if plan is not None:
         params.fft_size = plan.frame
     ctx = dl.Context(params, psfs)
     if plan is not None:
         ctx.set_plan(plan)
     x_dev = torch.tensor(scene.astype(np.float32), device="cuda")
     blurred = ctx.blur_global(x_dev).cpu().numpy().astype(np.float64)
+    del x_dev
     y, W = workloads.observe(blurred, w.noise, w.seed)
+    del blurred
     ctx.set_observation(torch.tensor(y.astype(np.float32), device="cuda"),
                         torch.tensor(W.astype(np.float32), device="cuda"))
     return ctx, w, scene, psfs, y, W, trials
@@ -95,6 +121,33 @@ def tile_bytes(ctx):
     out["col_H"] += nodes * HP
     out["col_Ht"] += nodes * HP
     return out
+
+
+def kernel_variant(ctx, kernel):
+    """Launch shape of one kernel family under the context's plan."""
+    pl = ctx.plan()
+    if kernel in ("col_H", "col_Ht"):
+        return {"frame": pl.frame, "waves": pl.col_waves, "tile_order": pl.tile_order}
+    if kernel == "consensus":
+        return {"frame": pl.frame}
+    return {"frame": pl.frame, "waves": pl.row_waves}
+
+
+def measured_traffic(ctx, workload, kernel):
+    """HBM bytes per launch of kernel from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary, if it was taken on the current kernel sources
+    and the same launch shape; else None."""
+    tfile = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.json")
+    if not os.path.exists(tfile):
+        return None
+    with open(tfile) as fh:
+        tj = json.load(fh)
+    if tj.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    k = tj.get("kernels", {}).get(kernel)
+    if not k or k.get("variant") != kernel_variant(ctx, kernel):
+        return None
+    return k.get("bytes_per_launch")
 
 
 def cpu_baseline(scene, psfs, y, W, w, budget_s=20.0):
@@ -196,6 +249,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the context's default launch plan")
+    ap.add_argument("--plan", default=None, help="fixed launch plan 'frame,col_waves,row_waves,order' "
+                                                 "(order: column_major | tile_major | heavy_first)")
+    ap.add_argument("--workload", default="batched", choices=sorted(WORKLOAD_TEXT),
+                    help="batched is the headline configuration; the others are reported the same way")
     ap.add_argument("--max-rounds", type=int, default=1500)
     ap.add_argument("--train-scenes", type=int, default=8)
     ap.add_argument("--train-steps", type=int, default=300)
@@ -218,7 +275,8 @@ def main():
         return
 
     print("# building workload", file=sys.stderr, flush=True)
-    ctx, w, scene, psfs, y, W, trials = build_workload(tune=not args.no_autotune)
+    ctx, w, scene, psfs, y, W, trials = build_workload(args.workload, tune=not args.no_autotune,
+                                                       plan=parse_plan(args.plan) if args.plan else None)
     n_outer, n_inner = w.n_outer, w.n_inner
     stream = torch.cuda.current_stream()
 
@@ -254,13 +312,7 @@ def main():
     per_step_ms = {k: kms[k] * iters for k in KERNELS_PER_STEP}
     dom = max(per_step_ms, key=per_step_ms.get)
     achieved = kb[dom] / (kms[dom] * 1e-3) / 1e9
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", f"{dom}_batched_hbm_traffic.json")
-    if os.path.exists(tfile):
-        with open(tfile) as fh:
-            tj = json.load(fh)
-        if tj.get("kernel_source_hash") == kernel_source_hash():
-            traffic = tj.get("bytes_per_launch")
+    traffic = measured_traffic(ctx, args.workload, dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": dom, "kernel_ms": round(kms[dom], 5),
@@ -272,9 +324,7 @@ def main():
         "metric": METRIC, "value": round(value, 2), "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "batched: 2048x2048 image, 8x8 tiles (32-px overlap, uneven edge tiles), "
-                               "8x8 grid of 31x31 Moffat PSFs, Poisson+read noise, smoothed TV + positivity, "
-                               "200 iterations (20 D-R rounds x 10 Local-Solver steps), one solve per step",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "global_pixels": w.M * w.M, "iterations": iters, "tiles": ctx.n_tiles,
                    "fft_frame": ctx.tiles[0].frame, "parallelism": "single GPU, all tiles batched",
                    "plan": ctx.plan().as_dict()},
@@ -288,10 +338,10 @@ def main():
         out["autotune"] = {"plans_measured": len(trials), "frames": sorted({t.frame for t in trials}),
                            "best": best.as_dict(), "default": dflt.as_dict(),
                            "worst_us_per_iter": round(max(t.us_per_iter for t in trials), 2)}
-    if not args.no_convergence:
+    if not args.no_convergence and args.workload == "batched":
         print("# convergence: plain vs warm start", file=sys.stderr, flush=True)
         out["convergence"] = convergence(ctx, w, args)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "batched":
         print("# cpu baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene, psfs, y, W, w, args.cpu_budget)
     ctx.close()

@@ -190,11 +190,13 @@ int deblur_step_sizes(deblur_ctx* ctx, float* tau_host);
  * observed pixel is taken from the tile whose block owns it. */
 int deblur_blur_global(deblur_ctx* ctx, const float* x_global, float* y_global);
 
-/* Kernel timing: launches each kernel of one Local-Solver step and of the
- * consensus step reps times between HIP events on the context stream and
- * writes the mean milliseconds per launch to ms_host[DEBLUR_N_KERNELS] in the
- * order col_H, row_resid, col_Ht, row_update, consensus.  The state (x, u)
- * is saved and restored around the measurement. */
+/* Kernel timing on the context stream: reps Local-Solver steps (after one
+ * warm-up step) with a HIP event between consecutive kernels, so each of the
+ * four kernels is timed where it runs in a D-R round, then reps launches of
+ * the consensus kernel.  Writes the mean milliseconds per launch to
+ * ms_host[DEBLUR_N_KERNELS] in the order col_H, row_resid, col_Ht,
+ * row_update, consensus.  The state (x, u) is saved and restored around the
+ * measurement. */
 enum { DEBLUR_N_KERNELS = 5 };
 int deblur_time_kernels(deblur_ctx* ctx, int32_t reps, float* ms_host);
 

@@ -337,7 +337,7 @@ void inner_step(deblur_ctx* c, hipStream_t s, int parity) {
 void consensus_launch(deblur_ctx* c, hipStream_t s, int parity) {
     hipLaunchKernelGGL(dbl::k_consensus, pix_grid(c), dim3(dbl::kPixBlock), 0, s, c->x[parity], c->u, c->covY,
                        c->covX, c->Xy, c->Xx, c->p.T_x, c->N, c->p.rho, c->cons_part);
-    hipLaunchKernelGGL(dbl::k_finalize_residual, dim3(1), dim3(256), 0, s, c->cons_part, c->cons_nparts,
+    hipLaunchKernelGGL(dbl::k_finalize_residual, dim3(1), dim3(dbl::kFinThreads), 0, s, c->cons_part, c->cons_nparts,
                        c->res_hist, c->res_counter, c->res_last, kResCap);
 }
 
@@ -974,39 +974,54 @@ int deblur_blur_global(deblur_ctx* c, const float* xg, float* yg) {
 int deblur_time_kernels(deblur_ctx* c, int32_t reps, float* ms) {
     if (!c || !ms || reps < 1) return fail(c, DEBLUR_E_ARG, "bad argument");
     if (!c->have_state) return fail(c, DEBLUR_E_STATE, "deblur_init must come first");
-    hipEvent_t e0, e1;
-    HIP_TRY(c, hipEventCreate(&e0));
-    HIP_TRY(c, hipEventCreate(&e1));
+    constexpr int K = 4;   // kernels of one Local-Solver step
+    hipEvent_t ev[K + 1];
+    for (hipEvent_t& e : ev) HIP_TRY(c, hipEventCreate(&e));
     const int cur = c->cur;
-    // u is modified by the consensus step: keep a copy
+    // the steps overwrite x[cur] (every second one) and the consensus step u: keep copies
     hipLaunchKernelGGL(dbl::k_copy, dim3(1024), dim3(256), 0, c->stream, c->u, c->frame_tmp, frame_elems(c));
-    for (int which = 0; which < DEBLUR_N_KERNELS; ++which) {
-        auto launch = [&]() {
-            switch (which) {
-                case 0: col_H(c, c->stream); break;
-                case 1: row_resid(c, c->stream); break;
-                case 2: col_Ht(c, c->stream); break;
-                case 3: row_update(c, c->stream, c->x[cur], c->x[1 - cur]); break;
-                default:
-                    hipLaunchKernelGGL(dbl::k_consensus, pix_grid(c), dim3(dbl::kPixBlock), 0, c->stream, c->x[cur],
-                                       c->u, c->covY, c->covX, c->Xy, c->Xx, c->p.T_x, c->N, c->p.rho, c->cons_part);
-                    break;
-            }
-        };
-        launch();   // warm-up
-        HIP_TRY(c, hipEventRecord(e0, c->stream));
-        for (int i = 0; i < reps; ++i) launch();
-        HIP_TRY(c, hipEventRecord(e1, c->stream));
-        HIP_TRY(c, hipEventSynchronize(e1));
-        float t = 0.f;
-        HIP_TRY(c, hipEventElapsedTime(&t, e0, e1));
-        ms[which] = t / reps;
+    hipLaunchKernelGGL(dbl::k_copy, dim3(1024), dim3(256), 0, c->stream, c->x[cur], c->frame_tmp2, frame_elems(c));
+    // Local-Solver kernels, timed one by one inside consecutive steps, as in a D-R round
+    double acc[K] = {0, 0, 0, 0};
+    int par = cur;
+    for (int i = 0; i <= reps; ++i) {   // step 0 is a warm-up
+        HIP_TRY(c, hipEventRecord(ev[0], c->stream));
+        col_H(c, c->stream);
+        HIP_TRY(c, hipEventRecord(ev[1], c->stream));
+        row_resid(c, c->stream);
+        HIP_TRY(c, hipEventRecord(ev[2], c->stream));
+        col_Ht(c, c->stream);
+        HIP_TRY(c, hipEventRecord(ev[3], c->stream));
+        row_update(c, c->stream, c->x[par], c->x[1 - par]);
+        HIP_TRY(c, hipEventRecord(ev[4], c->stream));
+        HIP_TRY(c, hipEventSynchronize(ev[4]));
+        par = 1 - par;
+        if (i == 0) continue;
+        for (int k = 0; k < K; ++k) {
+            float t = 0.f;
+            HIP_TRY(c, hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+            acc[k] += t;
+        }
     }
+    for (int k = 0; k < K; ++k) ms[k] = (float)(acc[k] / reps);
+    hipLaunchKernelGGL(dbl::k_copy, dim3(1024), dim3(256), 0, c->stream, c->frame_tmp2, c->x[cur], frame_elems(c));
+    // consensus step, repeated on the same (x, u)
+    auto cons = [&]() {
+        hipLaunchKernelGGL(dbl::k_consensus, pix_grid(c), dim3(dbl::kPixBlock), 0, c->stream, c->x[cur], c->u, c->covY,
+                           c->covX, c->Xy, c->Xx, c->p.T_x, c->N, c->p.rho, c->cons_part);
+    };
+    cons();
+    HIP_TRY(c, hipEventRecord(ev[0], c->stream));
+    for (int i = 0; i < reps; ++i) cons();
+    HIP_TRY(c, hipEventRecord(ev[1], c->stream));
+    HIP_TRY(c, hipEventSynchronize(ev[1]));
+    float t = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&t, ev[0], ev[1]));
+    ms[K] = t / reps;
     hipLaunchKernelGGL(dbl::k_copy, dim3(1024), dim3(256), 0, c->stream, c->frame_tmp, c->u, frame_elems(c));
     refresh_spectra(c, c->stream);
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (hipEvent_t& e : ev) (void)hipEventDestroy(e);
     return check_launch(c, "time_kernels");
 }
 

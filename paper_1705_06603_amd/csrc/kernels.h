@@ -958,29 +958,40 @@ __global__ __launch_bounds__(kPixBlock) void k_consensus(const float* __restrict
 
 // Fixed-order reduction of the consensus partials into the residual
 // ||u_new - u_old|| / ||u_new||, written to hist[*counter] and *last.
-__global__ __launch_bounds__(256) void k_finalize_residual(const float2* __restrict__ part, int np,
-                                                          double* __restrict__ hist, int* __restrict__ counter,
-                                                          double* __restrict__ last, int cap) {
-    __shared__ double sa[256], sb[256];
+// Thread t sums partials t, t + 1024, ... in that order; the 1024 sums are
+// combined by a fixed butterfly in each wave and then wave by wave.
+constexpr int kFinThreads = 1024;
+__global__ __launch_bounds__(kFinThreads) void k_finalize_residual(const float2* __restrict__ part, int np,
+                                                                  double* __restrict__ hist,
+                                                                  int* __restrict__ counter,
+                                                                  double* __restrict__ last, int cap) {
+    __shared__ double sa[kFinThreads / 64], sb[kFinThreads / 64];
     const int tid = threadIdx.x;
     double a = 0.0, b = 0.0;
-    for (int i = tid; i < np; i += 256) {
-        a += (double)part[i].x;
-        b += (double)part[i].y;
+#pragma unroll 8
+    for (int i = tid; i < np; i += kFinThreads) {
+        const float2 p = part[i];
+        a += (double)p.x;
+        b += (double)p.y;
     }
-    sa[tid] = a;
-    sb[tid] = b;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+    }
+    if ((tid & 63) == 0) {
+        sa[tid >> 6] = a;
+        sb[tid >> 6] = b;
+    }
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) {
-            sa[tid] += sa[tid + o];
-            sb[tid] += sb[tid + o];
-        }
-        __syncthreads();
-    }
     if (tid == 0) {
-        const double res = sb[0] > 0.0 ? sqrt(sa[0] / sb[0]) : 0.0;
-        const double out = (isfinite(sa[0]) && isfinite(sb[0])) ? res : (double)NAN;
+        double A = 0.0, B = 0.0;
+        for (int w = 0; w < kFinThreads / 64; ++w) {
+            A += sa[w];
+            B += sb[w];
+        }
+        const double res = B > 0.0 ? sqrt(A / B) : 0.0;
+        const double out = (isfinite(A) && isfinite(B)) ? res : (double)NAN;
         *last = out;
         const int k = *counter;
         if (k < cap) hist[k] = out;
