@@ -722,12 +722,14 @@ constexpr int kSeg = 8;
 // Phase 1: per mask k, transposed load of G_k, row C2R, accumulate b_k . (.)
 //          into the data gradient (registers), then park it in LDS as
 //          natural [row][col] floats.
-// Phase 2: one thread per (column, 8-row segment): walks down the rows
-//          carrying x at columns c-1, c, c+1 and the vertical term of the
-//          row above, so each pixel loads one new row triple and evaluates
-//          two regulariser scales; writes the new x to HBM and to LDS.
-// Phase 3: each wave reads its rows of the new x from LDS and, per mask k,
-//          does the forward row FFT and the transposed store of Z_k.
+// Phase 2: strips of 8 rows walked top to bottom, carrying the vertical flux
+//          of the row above: with Neumann differences a wave owns 62
+//          columns of a strip and takes horizontal neighbours from adjacent
+//          lanes (one regulariser scale per pixel); with circular
+//          differences a thread owns one column and loads x at c - 1, c and
+//          c + 1.  Writes the new x frame.
+// Phase 3: each wave re-reads its rows of the new x (an L2 hit) and, per mask
+//          k, does the forward row FFT and the transposed store of Z_k.
 template <int N, int WV>
 __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
         const float2* __restrict__ Gk, const float* __restrict__ xc, const float* __restrict__ u,
@@ -790,7 +792,83 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
         const bool circ = P.bc != 0;
         constexpr int SEGS = C::RB / kSeg;
         constexpr int TASKS = N * SEGS / C::NT;   // per thread (5 for every frame size)
-        // Two tasks per step: their loads are issued together.
+        if (!circ) {
+            // Neumann differences: wave-wide strips.  A task is kSeg rows of
+            // 64 consecutive columns c0 - 1 .. c0 + 62; lanes 1..62 own their
+            // column, lanes 0 and 63 are halo.  Each lane evaluates the
+            // regulariser scale of its own pixel once; x(i, c + 1) and the
+            // left neighbour's horizontal flux s gh come from the adjacent
+            // lanes.  The loads of a wave's next task are issued before the
+            // current task is computed (two register buffers).
+            constexpr int OWN = kLanes - 2;
+            constexpr int NCG = (N + OWN - 1) / OWN;
+            constexpr int NTASK = NCG * SEGS;
+            auto load = [&](int task, float (&X)[kSeg + 2], float (&U)[kSeg]) {
+                const int c = (task % NCG) * OWN - 1 + lane;
+                const int ia = i0 + (task / NCG) * kSeg;
+                const bool colin = c >= 0 && c < sx;
+#pragma unroll
+                for (int j = 0; j < kSeg + 2; ++j) {
+                    const int rr = ia - 1 + j;
+                    X[j] = (colin && rr >= 0 && rr < sy) ? xt[rr * N + c] : 0.f;
+                }
+#pragma unroll
+                for (int k = 0; k < kSeg; ++k) U[k] = (colin && ia + k < sy) ? ut[(ia + k) * N + c] : 0.f;
+            };
+            auto update = [&](int task, const float (&X)[kSeg + 2], const float (&U)[kSeg]) {
+                const int c = (task % NCG) * OWN - 1 + lane;
+                const int ia = i0 + (task / NCG) * kSeg;
+                const bool colin = c >= 0 && c < sx;
+                const bool rin = c + 1 < sx;   // the right neighbour is in the support
+                // vertical flux of the row above the strip
+                float qv_up = 0.f;
+                {
+                    const float xr = __shfl_down(X[0], 1);
+                    if (colin && ia >= 1 && ia < sy) {
+                        const float gh = rin ? xr - X[0] : 0.f;
+                        const float gv = X[1] - X[0];
+                        qv_up = reg_scale(gh, gv, P) * gv;
+                    }
+                }
+                const float oxc = colin ? ox[c] : 0.f;
+#pragma unroll
+                for (int k = 0; k < kSeg; ++k) {
+                    const int i = ia + k;
+                    const bool pin = colin && i < sy;
+                    const float xm = X[k + 1];
+                    const float xr = __shfl_down(xm, 1);
+                    const float gh = (pin && rin) ? xr - xm : 0.f;
+                    const float gv = (pin && i + 1 < sy) ? X[k + 2] - xm : 0.f;
+                    const float sc = reg_scale(gh, gv, P);
+                    const float qh = sc * gh, qv = sc * gv;
+                    const float qh_l = __shfl_up(qh, 1);
+                    float val = 0.f;
+                    if (pin) {
+                        // -div of the flux (s gh, s gv): backward differences
+                        const float g = (qh_l - qh) + (qv_up - qv);
+                        const float alpha = P.gamma * oy[i] * oxc;
+                        const float grad = sg[(i - i0) * N + c] + P.lambda * g + alpha * (xm - U[k]);
+                        val = xm - tt * grad;
+                        if (P.positivity) val = fmaxf(val, 0.f);
+                    }
+                    qv_up = qv;
+                    if (lane >= 1 && lane <= OWN && c < N) xo[i * N + c] = val;
+                }
+            };
+            float XA[kSeg + 2], UA[kSeg], XB[kSeg + 2], UB[kSeg];
+            if (wave < NTASK) load(wave, XA, UA);
+            for (int task = wave; task < NTASK; task += 2 * C::W) {
+                const int tb = task + C::W;
+                if (tb < NTASK) load(tb, XB, UB);
+                update(task, XA, UA);
+                if (tb >= NTASK) break;
+                if (tb + C::W < NTASK) load(tb + C::W, XA, UA);
+                update(tb, XB, UB);
+            }
+        } else
+        // Circular differences: one thread per (column, kSeg rows), x at
+        // c - 1, c, c + 1 loaded per row.  Two tasks per step: their loads
+        // are issued together.
         for (int t2 = 0; t2 < TASKS; t2 += 2) {
             float X[2][kSeg + 2][3];
             float U[2][kSeg];
