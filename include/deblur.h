@@ -131,10 +131,13 @@ int deblur_tile_layout(const deblur_ctx* ctx, deblur_tile_desc* desc_host, int32
                        int64_t* support_total, int64_t* block_total);
 
 /* Set the observation: y and w are device [M_y][M_x]; w = NULL means W = 1.
- * W is the inverse-variance weight of Eq. (3) (0 marks unmeasured pixels)
- * and must be finite and >= 0.  Computes each tile's step size
- * tau_t = 1 / (max_Bt W * max_Bt (H_t 1) + lambda * L_phi + gamma), with
- * L_phi = 8/eps (TV) or 8 (Huber). */
+ * W is the inverse-variance weight of Eq. (3) (0 marks unmeasured pixels).
+ * y must be finite and W finite and >= 0 on every block, else DEBLUR_E_ARG
+ * (the context then keeps neither an observation nor a state: set a valid
+ * observation and call deblur_init again).  A successful call keeps the
+ * current state (x, u), so a solve can be resumed on new data.  Computes each tile's step size
+ * tau_t = 1 / (max_Bt W * max_Bt (H_t 1) + lambda * L_phi + gamma * max omega_t),
+ * with L_phi = 8/eps (TV) or 8 (Huber). */
 int deblur_set_observation(deblur_ctx* ctx, const float* y, const float* w);
 
 /* Forward operator of every tile (Section II-B):

@@ -123,65 +123,94 @@ __global__ __launch_bounds__(256) void k_conv_in(const float* __restrict__ x, co
 // 32 -> 32 convolution on MFMA.  Epilogue:
 //   forward:  out = bf16(relu(acc + bias))
 //   backward: out = bf16(acc) where mask[p][c] > 0, else 0   (bias == nullptr)
-// Outside the valid region the output is 0.  One wave = 16 pixels x 32
-// channels; a workgroup of 4 waves covers 64 consecutive pixels of a row.
+// Outside the valid region the output is 0.  A wave covers kMidSeg
+// consecutive pixels of one row, 16 at a time (16 pixels x 32 channels: two
+// 16 x 16 accumulators); it keeps the B operands of all 9 taps (the 18 KB
+// weight block, 72 registers per lane) in registers for the whole segment,
+// so each 16-pixel step only loads its 9 A operands.  A workgroup of 4 waves
+// covers 4 rows.
+constexpr int kMidSeg = 160;
+constexpr int kMidRows = 4;
 __global__ __launch_bounds__(256) void k_conv_mid(const unsigned short* __restrict__ in,
                                                   const ImgDesc* __restrict__ desc, int H, int W,
                                                   const unsigned short* __restrict__ wgt,
                                                   const float* __restrict__ bias,
                                                   const unsigned short* __restrict__ mask,
                                                   unsigned short* __restrict__ out) {
-    __shared__ uint4 swt[9 * C * C / 8];           // bf16 weights [tap][co][ci], 18 KB
-    __shared__ unsigned short stage[4][16 * C];    // per-wave output staging
-    for (int i = threadIdx.x; i < 9 * C * C / 8; i += 256) swt[i] = reinterpret_cast<const uint4*>(wgt)[i];
-    __syncthreads();
+    __shared__ unsigned short stage[kMidRows][16 * C];    // per-wave output staging
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int b = blockIdx.z, y = blockIdx.y;
-    const int x0 = blockIdx.x * 64 + wave * 16;
-    if (x0 >= W) return;
+    const int b = blockIdx.z, y = blockIdx.y * kMidRows + wave;
+    const int xbeg = blockIdx.x * kMidSeg;
+    if (y >= H) return;   // no workgroup barrier below
     const ImgDesc d = desc[b];
     const int li = lane & 15, lk = lane >> 4;        // row/col index and k group
-    f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-    const unsigned short* ib = in + (size_t)b * H * W * C;
+    uint4 bw0[9], bw1[9];
+    const uint4* wq = reinterpret_cast<const uint4*>(wgt);
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-        const int yy = y + t / 3 - 1, xs = x0 + li + t % 3 - 1;
-        uint4 av = make_uint4(0, 0, 0, 0);
-        if (inside(d, yy, xs)) av = *reinterpret_cast<const uint4*>(ib + ((size_t)yy * W + xs) * C + 8 * lk);
-        const uint4 b0 = swt[((t * C + li) * C + 8 * lk) / 8];
-        const uint4 b1 = swt[((t * C + 16 + li) * C + 8 * lk) / 8];
-        const bf16x8 A = __builtin_bit_cast(bf16x8, av);
-        acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, b0), acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, b1), acc1, 0, 0, 0);
+        bw0[t] = wq[((t * C + li) * C + 8 * lk) / 8];
+        bw1[t] = wq[((t * C + 16 + li) * C + 8 * lk) / 8];
     }
-    // D: column co = li (+16), rows (pixels) 4 lk .. 4 lk + 3
+    float b0v = 0.f, b1v = 0.f;
+    if (bias) {
+        b0v = bias[li];
+        b1v = bias[16 + li];
+    }
+    const unsigned short* ib = in + (size_t)b * H * W * C;
     unsigned short* st = stage[wave];
+    const int xend = min(W, xbeg + kMidSeg);
+    for (int x0 = xbeg; x0 < xend; x0 += 16) {
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        uint4 av[9];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int px = 4 * lk + r;
-        const int xs = x0 + px;
-        float v0 = acc0[r], v1 = acc1[r];
-        if (bias) {
-            v0 = fmaxf(v0 + bias[li], 0.f);
-            v1 = fmaxf(v1 + bias[16 + li], 0.f);
-        } else {
-            const size_t mi = (((size_t)b * H + y) * W + (xs < W ? xs : 0)) * C;
-            if (!(xs < W && bf2f(mask[mi + li]) > 0.f)) v0 = 0.f;
-            if (!(xs < W && bf2f(mask[mi + 16 + li]) > 0.f)) v1 = 0.f;
+        for (int t = 0; t < 9; ++t) {
+            const int yy = y + t / 3 - 1, xs = x0 + li + t % 3 - 1;
+            av[t] = make_uint4(0, 0, 0, 0);
+            if (inside(d, yy, xs)) av[t] = *reinterpret_cast<const uint4*>(ib + ((size_t)yy * W + xs) * C + 8 * lk);
         }
-        if (!inside(d, y, xs)) v0 = v1 = 0.f;
-        st[px * C + li] = f2bf(v0);
-        st[px * C + 16 + li] = f2bf(v1);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const bf16x8 A = __builtin_bit_cast(bf16x8, av[t]);
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, bw0[t]), acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, bw1[t]), acc1, 0, 0, 0);
+        }
+        // D: column co = li (+16), rows (pixels) 4 lk .. 4 lk + 3
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int px = 4 * lk + r;
+            const int xs = x0 + px;
+            float v0 = acc0[r], v1 = acc1[r];
+            if (bias) {
+                v0 = fmaxf(v0 + b0v, 0.f);
+                v1 = fmaxf(v1 + b1v, 0.f);
+            } else {
+                const size_t mi = (((size_t)b * H + y) * W + (xs < W ? xs : 0)) * C;
+                if (!(xs < W && bf2f(mask[mi + li]) > 0.f)) v0 = 0.f;
+                if (!(xs < W && bf2f(mask[mi + 16 + li]) > 0.f)) v1 = 0.f;
+            }
+            if (!inside(d, y, xs)) v0 = v1 = 0.f;
+            st[px * C + li] = f2bf(v0);
+            st[px * C + 16 + li] = f2bf(v1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // 16 pixels x 64 bytes: 4 lanes per pixel, 16 bytes each
+        {
+            const int px = lane >> 2, q = lane & 3;
+            if (x0 + px < W) {
+                const uint4 v = reinterpret_cast<const uint4*>(st + px * C)[q];
+                reinterpret_cast<uint4*>(out + (((size_t)b * H + y) * W + x0 + px) * C)[q] = v;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // 16 pixels x 64 bytes: 4 lanes per pixel, 16 bytes each
-    const int px = lane >> 2, q = lane & 3;
-    if (x0 + px < W) {
-        const uint4 v = reinterpret_cast<const uint4*>(st + px * C)[q];
-        reinterpret_cast<uint4*>(out + (((size_t)b * H + y) * W + x0 + px) * C)[q] = v;
-    }
+}
+
+inline dim3 conv_mid_grid(int B, int H, int W) {
+    return dim3((W + kMidSeg - 1) / kMidSeg, (H + kMidRows - 1) / kMidRows, B);
 }
 
 // Layer 4 (32 -> 1) plus residual, thread per pixel: out = x + conv(a3) + b4.

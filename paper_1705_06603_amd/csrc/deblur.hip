@@ -648,7 +648,7 @@ int compute_rowsums(deblur_ctx* c) {
                        c->frame_tmp2);
     apply_H_frames(c, c->stream, c->frame_tmp2, c->frame_tmp);
     hipLaunchKernelGGL(dbl::k_block_max, dim3(c->nt), dim3(256), 0, c->stream, c->frame_tmp, 1, 0, c->tiles, c->N,
-                       c->r, c->rowsum);
+                       c->r, c->rowsum, 0);
     int rc = check_launch(c, "row sums");
     if (rc) return rc;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -758,20 +758,29 @@ int deblur_tile_layout(const deblur_ctx* c, deblur_tile_desc* desc, int32_t cap,
 
 int deblur_set_observation(deblur_ctx* c, const float* y, const float* w) {
     if (!c || !y) return fail(c, DEBLUR_E_ARG, "null argument");
+    // a failed call leaves neither an observation nor a state to iterate on
+    const bool had_state = c->have_state;
+    c->have_obs = false;
+    c->have_state = false;
     hipLaunchKernelGGL(dbl::k_copy, dim3(1024), dim3(256), 0, c->stream, y, c->y_glob,
                        (size_t)c->p.M_y * c->p.M_x);
     hipLaunchKernelGGL(dbl::k_set_obs, frame_grid(c), dim3(256), 0, c->stream, y, w, c->tiles, c->borg, c->p.M_x,
                        c->N, c->r, c->yw);
     hipLaunchKernelGGL(dbl::k_block_max, dim3(c->nt), dim3(256), 0, c->stream, reinterpret_cast<float*>(c->yw), 2, 1,
-                       c->tiles, c->N, c->r, c->maxW);
+                       c->tiles, c->N, c->r, c->maxW, 1);
+    // y checked for finiteness the same way (frame_tmp is free scratch here)
+    hipLaunchKernelGGL(dbl::k_block_max, dim3(c->nt), dim3(256), 0, c->stream, reinterpret_cast<float*>(c->yw), 2, 0,
+                       c->tiles, c->N, c->r, c->frame_tmp, 0);
     int rc = check_launch(c, "set_observation");
     if (rc) return rc;
-    std::vector<float> mw(c->nt), rs(c->nt), tau(c->nt);
+    std::vector<float> mw(c->nt), my(c->nt), rs(c->nt), tau(c->nt);
     HIP_TRY(c, hipMemcpyAsync(mw.data(), c->maxW, c->nt * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(my.data(), c->frame_tmp, c->nt * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(rs.data(), c->rowsum, c->nt * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const double Lphi = (c->p.reg == DEBLUR_REG_SMOOTH_TV) ? 8.0 / c->p.reg_param : 8.0;
     for (int t = 0; t < c->nt; ++t) {
+        if (!std::isfinite(my[t])) return fail(c, DEBLUR_E_ARG, "y must be finite");
         if (!std::isfinite(mw[t]) || mw[t] < 0.f) return fail(c, DEBLUR_E_ARG, "W must be finite and >= 0");
         const double L = (double)mw[t] * rs[t] + (double)c->p.lambda * Lphi + (double)c->p.gamma * c->omega_max[t];
         tau[t] = (float)(1.0 / L);
@@ -779,6 +788,7 @@ int deblur_set_observation(deblur_ctx* c, const float* y, const float* w) {
     HIP_TRY(c, hipMemcpyAsync(c->tau, tau.data(), c->nt * 4, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->have_obs = true;
+    c->have_state = had_state;
     return DEBLUR_OK;
 }
 
@@ -1268,7 +1278,7 @@ void net_prep(deblur_cnn* n) {
 void net_forward(deblur_cnn* n, const float* img, int B, int H, int W) {
     hipLaunchKernelGGL(K::k_conv_in, pix_grid_cnn(B, H, W), dim3(256), 0, n->stream, img, n->desc, H, W, n->w1,
                        n->master, n->a1);
-    const dim3 mg((W + 63) / 64, H, B);
+    const dim3 mg = K::conv_mid_grid(B, H, W);
     hipLaunchKernelGGL(K::k_conv_mid, mg, dim3(256), 0, n->stream, n->a1, n->desc, H, W, n->wf2, n->master + K::kB2,
                        nullptr, n->a2);
     hipLaunchKernelGGL(K::k_conv_mid, mg, dim3(256), 0, n->stream, n->a2, n->desc, H, W, n->wf3, n->master + K::kB3,
@@ -1318,7 +1328,7 @@ int net_loss_grad(deblur_cnn* n, const float* img, const float* target, int B, i
     // layer 3
     hipLaunchKernelGGL(K::k_wgrad_mid, wg, dim3(256), 0, n->stream, n->dpA, n->a2, n->desc, H, W, n->part);
     net_reduce(n, nchunk, 9 * K::C * K::C + K::C, 9 * K::C * K::C, K::kW3, K::C, K::kB3, 9 * K::C * K::C);
-    const dim3 mg((W + 63) / 64, H, B);
+    const dim3 mg = K::conv_mid_grid(B, H, W);
     hipLaunchKernelGGL(K::k_conv_mid, mg, dim3(256), 0, n->stream, n->dpA, n->desc, H, W, n->wb3, nullptr, n->a2,
                        n->dpB);
     // layer 2
@@ -1505,7 +1515,7 @@ int deblur_cnn_time_forward(deblur_cnn* n, const float* img, int32_t B, int32_t 
     HIP_TRY_N(n, hipEventRecord(e0, n->stream));
     for (int i = 0; i < reps; ++i) net_forward(n, img, B, H, W);
     HIP_TRY_N(n, hipEventRecord(e1, n->stream));
-    const dim3 mg((W + 63) / 64, H, B);
+    const dim3 mg = K::conv_mid_grid(B, H, W);
     for (int i = 0; i < reps; ++i)
         hipLaunchKernelGGL(K::k_conv_mid, mg, dim3(256), 0, n->stream, n->a1, n->desc, H, W, n->wf2,
                            n->master + K::kB2, nullptr, n->a2);

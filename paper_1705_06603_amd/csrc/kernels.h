@@ -1207,24 +1207,30 @@ __global__ void k_fill(float* __restrict__ a, float v, size_t n) {
 
 // Per-tile maximum over the block region of a frame array (stride 1) or of the
 // W component of the (y, W) frames (stride 2, offset 1).
+// Per tile: the maximum over the block of a frame component, or NaN if a
+// value there is not finite (or, with nonneg, negative).
 __global__ __launch_bounds__(256) void k_block_max(const float* __restrict__ fr, int stride, int off,
                                                   const TileInfo* __restrict__ tiles, int N, int r,
-                                                  float* __restrict__ out) {
+                                                  float* __restrict__ out, int nonneg) {
     __shared__ float red[256];
     const int t = blockIdx.x;
     const TileInfo ti = tiles[t];
     float m = -INFINITY;
+    int bad = 0;
     for (int e = threadIdx.x; e < ti.by * ti.bx; e += 256) {
         const int i = e / ti.bx + r, c = e % ti.bx + r;
-        m = fmaxf(m, fr[((size_t)t * N * N + (size_t)i * N + c) * stride + off]);
+        const float v = fr[((size_t)t * N * N + (size_t)i * N + c) * stride + off];
+        bad |= !isfinite(v) || (nonneg && v < 0.f);
+        m = fmaxf(m, v);
     }
+    bad = __syncthreads_or(bad);
     red[threadIdx.x] = m;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (threadIdx.x < o) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + o]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[t] = red[0];
+    if (threadIdx.x == 0) out[t] = bad ? NAN : red[0];
 }
 
 // Regulariser value and metric term per tile and row block:

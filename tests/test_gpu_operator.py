@@ -18,6 +18,10 @@ CASES = [
     (256, 2, 128, 16, 15, 2, "interp", {}),                          # small workload geometry
     (300, 3, 110, 10, 9, 3, "interp", dict(M_x=290, T_x=3, G_x=2)),  # uneven edge tiles, N = 160
     (600, 2, 300, 20, 21, 2, "interp", {}),                          # N = 640
+    (37, 1, 37, 0, 5, 1, "interp", {}),                              # one tile, one PSF
+    (50, 1, 50, 0, 7, 3, "interp", {}),                              # one tile, 3 x 3 nodes
+    (40, 2, 20, 4, 1, 2, "interp", {}),                              # P = 1: no blur
+    (24, 3, 8, 0, 3, 3, "local", {}),                                # zero overlap, 8-px blocks
 ]
 
 
