@@ -123,25 +123,47 @@ __global__ __launch_bounds__(256) void k_conv_in(const float* __restrict__ x, co
 // 32 -> 32 convolution on MFMA.  Epilogue:
 //   forward:  out = bf16(relu(acc + bias))
 //   backward: out = bf16(acc) where mask[p][c] > 0, else 0   (bias == nullptr)
-// Outside the valid region the output is 0.  A wave covers kMidSeg
-// consecutive pixels of one row, 16 at a time (16 pixels x 32 channels: two
-// 16 x 16 accumulators); it keeps the B operands of all 9 taps (the 18 KB
-// weight block, 72 registers per lane) in registers for the whole segment,
-// so each 16-pixel step only loads its 9 A operands.  A workgroup of 4 waves
-// covers 4 rows.
+// Outside the valid region the output is 0.  A wave computes two output rows
+// over kMidSeg consecutive pixels, 16 pixels at a time (16 pixels x 32
+// channels per row: two 16 x 16 accumulators).  It keeps the B operands of
+// all 9 taps (the 18 KB weight block, 72 registers per lane) in registers for
+// the whole segment.  Per 16-pixel step it loads the four input rows the two
+// output rows need, one 16-byte A fragment per lane and row (pixel x0 + l,
+// channels 8k .. 8k + 7), plus the pixel just left or right of the step for
+// the edge lanes; the A operands of the taps at dx = -1 and +1 are the same
+// fragments shifted by one lane inside each 16-lane row (DPP row_shr:1 and
+// row_shl:1).  A workgroup of 4 waves covers 8 rows.
 constexpr int kMidSeg = 160;
-constexpr int kMidRows = 4;
+constexpr int kMidRows = 8;   // output rows per workgroup (2 per wave)
+
+__device__ __forceinline__ uint4 dpp_row_shift(uint4 v, bool right) {
+    // right: lane l of each 16-lane row receives lane l - 1's value; else lane l + 1's
+    uint4 o;
+    if (right) {
+        o.x = __builtin_amdgcn_update_dpp(0u, v.x, 0x111, 0xf, 0xf, true);
+        o.y = __builtin_amdgcn_update_dpp(0u, v.y, 0x111, 0xf, 0xf, true);
+        o.z = __builtin_amdgcn_update_dpp(0u, v.z, 0x111, 0xf, 0xf, true);
+        o.w = __builtin_amdgcn_update_dpp(0u, v.w, 0x111, 0xf, 0xf, true);
+    } else {
+        o.x = __builtin_amdgcn_update_dpp(0u, v.x, 0x101, 0xf, 0xf, true);
+        o.y = __builtin_amdgcn_update_dpp(0u, v.y, 0x101, 0xf, 0xf, true);
+        o.z = __builtin_amdgcn_update_dpp(0u, v.z, 0x101, 0xf, 0xf, true);
+        o.w = __builtin_amdgcn_update_dpp(0u, v.w, 0x101, 0xf, 0xf, true);
+    }
+    return o;
+}
+
 __global__ __launch_bounds__(256) void k_conv_mid(const unsigned short* __restrict__ in,
                                                   const ImgDesc* __restrict__ desc, int H, int W,
                                                   const unsigned short* __restrict__ wgt,
                                                   const float* __restrict__ bias,
                                                   const unsigned short* __restrict__ mask,
                                                   unsigned short* __restrict__ out) {
-    __shared__ unsigned short stage[kMidRows][16 * C];    // per-wave output staging
+    __shared__ unsigned short stage[4][16 * C];    // per-wave output staging
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int b = blockIdx.z, y = blockIdx.y * kMidRows + wave;
+    const int b = blockIdx.z, y0 = blockIdx.y * kMidRows + 2 * wave;
     const int xbeg = blockIdx.x * kMidSeg;
-    if (y >= H) return;   // no workgroup barrier below
+    if (y0 >= H) return;   // no workgroup barrier below
     const ImgDesc d = desc[b];
     const int li = lane & 15, lk = lane >> 4;        // row/col index and k group
     uint4 bw0[9], bw1[9];
@@ -159,53 +181,72 @@ __global__ __launch_bounds__(256) void k_conv_mid(const unsigned short* __restri
     const unsigned short* ib = in + (size_t)b * H * W * C;
     unsigned short* st = stage[wave];
     const int xend = min(W, xbeg + kMidSeg);
+    // the pixel an edge lane needs besides its own: x0 - 1 (l = 0) or x0 + 16 (l = 15)
+    const int edge_dx = li == 0 ? -1 : (li == 15 ? 16 : li);
     for (int x0 = xbeg; x0 < xend; x0 += 16) {
-        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-        uint4 av[9];
+        uint4 cen[4], edg[4];   // input rows y0 - 1 .. y0 + 2: own pixel, edge pixel
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int yy = y + t / 3 - 1, xs = x0 + li + t % 3 - 1;
-            av[t] = make_uint4(0, 0, 0, 0);
-            if (inside(d, yy, xs)) av[t] = *reinterpret_cast<const uint4*>(ib + ((size_t)yy * W + xs) * C + 8 * lk);
+        for (int rr = 0; rr < 4; ++rr) {
+            const int yy = y0 - 1 + rr;
+            const int xc = x0 + li, xe = x0 + edge_dx;
+            cen[rr] = make_uint4(0, 0, 0, 0);
+            edg[rr] = make_uint4(0, 0, 0, 0);
+            if (inside(d, yy, xc)) cen[rr] = *reinterpret_cast<const uint4*>(ib + ((size_t)yy * W + xc) * C + 8 * lk);
+            if ((li == 0 || li == 15) && inside(d, yy, xe))
+                edg[rr] = *reinterpret_cast<const uint4*>(ib + ((size_t)yy * W + xe) * C + 8 * lk);
         }
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const bf16x8 A = __builtin_bit_cast(bf16x8, av[t]);
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, bw0[t]), acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, bw1[t]), acc1, 0, 0, 0);
-        }
-        // D: column co = li (+16), rows (pixels) 4 lk .. 4 lk + 3
+        for (int h = 0; h < 2; ++h) {
+            const int y = y0 + h;
+            if (y >= H) break;
+            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int px = 4 * lk + r;
-            const int xs = x0 + px;
-            float v0 = acc0[r], v1 = acc1[r];
-            if (bias) {
-                v0 = fmaxf(v0 + b0v, 0.f);
-                v1 = fmaxf(v1 + b1v, 0.f);
-            } else {
-                const size_t mi = (((size_t)b * H + y) * W + (xs < W ? xs : 0)) * C;
-                if (!(xs < W && bf2f(mask[mi + li]) > 0.f)) v0 = 0.f;
-                if (!(xs < W && bf2f(mask[mi + 16 + li]) > 0.f)) v1 = 0.f;
+            for (int t = 0; t < 9; ++t) {
+                const int rr = h + t / 3, dx = t % 3;
+                uint4 a = cen[rr];
+                if (dx != 1) {
+                    // the shift runs on all lanes (a lane reading a masked-off
+                    // lane would get 0), then the edge lane takes its own load
+                    const uint4 sh = dpp_row_shift(a, dx == 0);
+                    a = (dx == 0 ? li == 0 : li == 15) ? edg[rr] : sh;
+                }
+                const bf16x8 Aop = __builtin_bit_cast(bf16x8, a);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop, __builtin_bit_cast(bf16x8, bw0[t]), acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop, __builtin_bit_cast(bf16x8, bw1[t]), acc1, 0, 0, 0);
             }
-            if (!inside(d, y, xs)) v0 = v1 = 0.f;
-            st[px * C + li] = f2bf(v0);
-            st[px * C + 16 + li] = f2bf(v1);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        // 16 pixels x 64 bytes: 4 lanes per pixel, 16 bytes each
-        {
-            const int px = lane >> 2, q = lane & 3;
-            if (x0 + px < W) {
-                const uint4 v = reinterpret_cast<const uint4*>(st + px * C)[q];
-                reinterpret_cast<uint4*>(out + (((size_t)b * H + y) * W + x0 + px) * C)[q] = v;
+            // D: column co = li (+16), rows (pixels) 4 lk .. 4 lk + 3
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int px = 4 * lk + r;
+                const int xs = x0 + px;
+                float v0 = acc0[r], v1 = acc1[r];
+                if (bias) {
+                    v0 = fmaxf(v0 + b0v, 0.f);
+                    v1 = fmaxf(v1 + b1v, 0.f);
+                } else {
+                    const size_t mi = (((size_t)b * H + y) * W + (xs < W ? xs : 0)) * C;
+                    if (!(xs < W && bf2f(mask[mi + li]) > 0.f)) v0 = 0.f;
+                    if (!(xs < W && bf2f(mask[mi + 16 + li]) > 0.f)) v1 = 0.f;
+                }
+                if (!inside(d, y, xs)) v0 = v1 = 0.f;
+                st[px * C + li] = f2bf(v0);
+                st[px * C + 16 + li] = f2bf(v1);
             }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // 16 pixels x 64 bytes: 4 lanes per pixel, 16 bytes each
+            {
+                const int px = lane >> 2, q = lane & 3;
+                if (x0 + px < W) {
+                    const uint4 v = reinterpret_cast<const uint4*>(st + px * C)[q];
+                    reinterpret_cast<uint4*>(out + (((size_t)b * H + y) * W + x0 + px) * C)[q] = v;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
