@@ -52,13 +52,15 @@ WORKLOAD_TEXT = {
 
 
 def parse_plan(text):
-    """'frame,col_waves,row_waves,order' with order a name or number."""
+    """'frame,col_waves,row_waves,order[,tile_groups]' with order a name or number."""
     from paper_1705_06603_amd import _lib as dl
-    f, cw, rw, order = text.split(",")
+    parts = text.split(",")
+    f, cw, rw, order = parts[:4]
     names = {v: k for k, v in dl.ORDER_NAMES.items()}
     pl = dl.Plan()
     pl.frame, pl.col_waves, pl.row_waves = int(f), int(cw), int(rw)
     pl.tile_order = names[order] if order in names else int(order)
+    pl.tile_groups = int(parts[4]) if len(parts) > 4 else 1
     return pl
 
 
@@ -249,8 +251,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the context's default launch plan")
-    ap.add_argument("--plan", default=None, help="fixed launch plan 'frame,col_waves,row_waves,order' "
-                                                 "(order: column_major | tile_major | heavy_first)")
+    ap.add_argument("--plan", default=None, help="fixed launch plan 'frame,col_waves,row_waves,order[,groups]' "
+                                                 "(order: column_major | tile_major | heavy_first; groups 1 or 2)")
     ap.add_argument("--workload", default="batched", choices=sorted(WORKLOAD_TEXT),
                     help="batched is the headline configuration; the others are reported the same way")
     ap.add_argument("--max-rounds", type=int, default=1500)

@@ -222,6 +222,12 @@ int deblur_time_kernels(deblur_ctx* ctx, int32_t reps, float* ms_host);
  *               DEBLUR_ORDER_HEAVY_FIRST   column-group-major over the tiles
  *                                          sorted by PSF term count, most
  *                                          first.
+ *   tile_groups 1: every kernel launch covers all tiles; 2: the tiles are
+ *               split into two groups (the first ceil(T/2) tiles and the
+ *               rest) whose Local-Solver steps run as two independent chains
+ *               of launches on two streams, joined before each consensus
+ *               step (two branches of the captured graph), so the kernels of
+ *               one group fill the GPU while the other's drain.
  * The iterates are bitwise identical under every plan: each pixel goes
  * through the same operations in the same order.  Only the grouping of the
  * partial sums of deblur_objective follows row_waves. */
@@ -235,6 +241,7 @@ typedef struct deblur_plan {
     int32_t col_waves;
     int32_t row_waves;
     int32_t tile_order;
+    int32_t tile_groups;
     float us_per_iter;    /* measured microseconds per iteration (all tiles'
                              Local-Solver step + 1/n_inner of a consensus
                              step) when the plan comes from deblur_autotune;
@@ -242,13 +249,13 @@ typedef struct deblur_plan {
 } deblur_plan;
 
 /* The context's plan (host out).  A new context starts with the frame it
- * chose, the larger workgroup shape for both kernel families and
- * DEBLUR_ORDER_COLUMN_MAJOR. */
+ * chose, the larger workgroup shape for both kernel families,
+ * DEBLUR_ORDER_COLUMN_MAJOR and one tile group. */
 int deblur_get_plan(const deblur_ctx* ctx, deblur_plan* plan_host);
 
 /* Replaces the context's plan (host in).  plan.frame must equal the
- * context's frame (0 is taken as that frame); waves and order must be among
- * the values above, else DEBLUR_E_ARG.  Synchronises the context stream and
+ * context's frame (0 is taken as that frame); waves, order and tile_groups
+ * must be among the values above, else DEBLUR_E_ARG.  Synchronises the context stream and
  * drops the captured graphs of deblur_run, which are re-captured with the
  * new shapes on their next use.  State and observation are kept. */
 int deblur_set_plan(deblur_ctx* ctx, const deblur_plan* plan_host);

@@ -62,12 +62,12 @@ class TileDesc(ctypes.Structure):
 class Plan(ctypes.Structure):
     _fields_ = [
         ("frame", ctypes.c_int32), ("col_waves", ctypes.c_int32), ("row_waves", ctypes.c_int32),
-        ("tile_order", ctypes.c_int32), ("us_per_iter", ctypes.c_float),
+        ("tile_order", ctypes.c_int32), ("tile_groups", ctypes.c_int32), ("us_per_iter", ctypes.c_float),
     ]
 
     def as_dict(self):
         return {"frame": self.frame, "col_waves": self.col_waves, "row_waves": self.row_waves,
-                "tile_order": ORDER_NAMES.get(self.tile_order, self.tile_order),
+                "tile_order": ORDER_NAMES.get(self.tile_order, self.tile_order), "tile_groups": self.tile_groups,
                 "us_per_iter": round(float(self.us_per_iter), 2)}
 
 
@@ -351,7 +351,7 @@ def autotune(params: Params, psfs, n_inner=10, reps=3, stream=None):
     L = lib()
     psf = np.ascontiguousarray(np.asarray(psfs, dtype=np.float32))
     best = Plan()
-    cap = 64
+    cap = 128
     trials = (Plan * cap)()
     n = ctypes.c_int32()
     rc = L.deblur_autotune(ctypes.byref(params), psf.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream),

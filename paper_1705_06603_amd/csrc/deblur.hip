@@ -157,7 +157,11 @@ struct deblur_ctx {
     // launch plan (frame fixed at creation; the rest set by deblur_set_plan)
     deblur_plan plan{};
     int* perm_id = nullptr;      // tile order tables of the column kernels
-    int* perm_heavy = nullptr;
+    int* perm_heavy = nullptr;   // all tiles by term count
+    int* perm_heavy2 = nullptr;  // each half of the tiles by term count (two tile groups)
+    hipStream_t aux_stream = nullptr;   // second branch of a round with two tile groups
+    hipStream_t cap_aux = nullptr;      // its counterpart during graph capture
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -214,26 +218,38 @@ void launch_row_inv(deblur_ctx* c, hipStream_t s, const float2* in, float* out, 
     hipLaunchKernelGGL((dbl::k_row_inv<N, WV>), dim3(C::RG, c->nt), dim3(C::NT), 0, s, in, c->tiles, c->tentX, c->tw,
                        out, masked);
 }
-const int* col_perm(const deblur_ctx* c) {
-    return c->plan.tile_order == DEBLUR_ORDER_HEAVY_FIRST ? c->perm_heavy : c->perm_id;
+// A contiguous range of tiles [t0, t0 + cnt) and the column kernels' order
+// of it (perm[0 .. cnt) are tile indices).
+struct TileRange {
+    int t0, cnt;
+    const int* perm;
+};
+TileRange all_tiles(const deblur_ctx* c) {
+    return {0, c->nt, c->plan.tile_order == DEBLUR_ORDER_HEAVY_FIRST ? c->perm_heavy : c->perm_id};
+}
+// Tile group g of two: the first ceil(T/2) tiles or the rest.
+TileRange tile_group(const deblur_ctx* c, int g) {
+    const int h = (c->nt + 1) / 2;
+    const int t0 = g ? h : 0, cnt = g ? c->nt - h : h;
+    return {t0, cnt, (c->plan.tile_order == DEBLUR_ORDER_HEAVY_FIRST ? c->perm_heavy2 : c->perm_id) + t0};
 }
 template <int N, int WV>
-void launch_col_H(deblur_ctx* c, hipStream_t s) {
+void launch_col_H(deblur_ctx* c, hipStream_t s, TileRange r) {
     using C = dbl::Cfg<N, WV>;
-    hipLaunchKernelGGL((dbl::k_col_H<N, WV>), dim3(dbl::col_grid<N, WV>(c->nt)), dim3(C::NT), 0, s, c->Zk, c->tiles,
-                       c->tentY, c->spec, c->tw, c->Yc, c->nt, col_perm(c), c->plan.tile_order);
+    hipLaunchKernelGGL((dbl::k_col_H<N, WV>), dim3(dbl::col_grid<N, WV>(r.cnt)), dim3(C::NT), 0, s, c->Zk, c->tiles,
+                       c->tentY, c->spec, c->tw, c->Yc, r.cnt, r.perm, c->plan.tile_order);
 }
 template <int N, int WV>
-void launch_row_resid(deblur_ctx* c, hipStream_t s) {
+void launch_row_resid(deblur_ctx* c, hipStream_t s, TileRange r) {
     using C = dbl::Cfg<N, WV>;
-    hipLaunchKernelGGL((dbl::k_row_resid<N, WV>), dim3(C::RG, c->nt), dim3(C::NT), 0, s, c->Yc, c->yw, c->tw, c->Rr,
-                       c->obj_part);
+    hipLaunchKernelGGL((dbl::k_row_resid<N, WV>), dim3(C::RG, r.cnt), dim3(C::NT), 0, s, c->Yc, c->yw, c->tw, c->Rr,
+                       c->obj_part, r.t0);
 }
 template <int N, int WV>
-void launch_col_Ht(deblur_ctx* c, hipStream_t s) {
+void launch_col_Ht(deblur_ctx* c, hipStream_t s, TileRange r) {
     using C = dbl::Cfg<N, WV>;
-    hipLaunchKernelGGL((dbl::k_col_Ht<N, WV>), dim3(dbl::col_grid<N, WV>(c->nt)), dim3(C::NT), 0, s, c->Rr, c->tiles,
-                       c->tentY, c->spec, c->tw, c->Gk, c->nt, col_perm(c), c->plan.tile_order);
+    hipLaunchKernelGGL((dbl::k_col_Ht<N, WV>), dim3(dbl::col_grid<N, WV>(r.cnt)), dim3(C::NT), 0, s, c->Rr, c->tiles,
+                       c->tentY, c->spec, c->tw, c->Gk, r.cnt, r.perm, c->plan.tile_order);
 }
 SolveParams solve_params(const deblur_ctx* c) {
     SolveParams P;
@@ -248,10 +264,10 @@ SolveParams solve_params(const deblur_ctx* c) {
     return P;
 }
 template <int N, int WV>
-void launch_row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn) {
+void launch_row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn, TileRange r) {
     using C = dbl::Cfg<N, WV>;
-    hipLaunchKernelGGL((dbl::k_row_update<N, WV>), dim3(C::RG, c->nt), dim3(C::NT), 0, s, c->Gk, xc, c->u, c->tiles,
-                       c->tentX, c->omY, c->omX, c->tau, solve_params(c), c->tw, xn, c->Zk);
+    hipLaunchKernelGGL((dbl::k_row_update<N, WV>), dim3(C::RG, r.cnt), dim3(C::NT), 0, s, c->Gk, xc, c->u, c->tiles,
+                       c->tentX, c->omY, c->omX, c->tau, solve_params(c), c->tw, xn, c->Zk, r.t0);
 }
 
 template <int N, int WV>
@@ -303,12 +319,18 @@ void row_fwd(deblur_ctx* c, hipStream_t s, const float* x, float2* out, int mask
 void row_inv(deblur_ctx* c, hipStream_t s, const float2* in, float* out, int masked) {
     DISPATCH_NW(c, c->plan.row_waves, launch_row_inv, s, in, out, masked);
 }
-void col_H(deblur_ctx* c, hipStream_t s) { DISPATCH_NW(c, c->plan.col_waves, launch_col_H, s); }
-void row_resid(deblur_ctx* c, hipStream_t s) { DISPATCH_NW(c, c->plan.row_waves, launch_row_resid, s); }
-void col_Ht(deblur_ctx* c, hipStream_t s) { DISPATCH_NW(c, c->plan.col_waves, launch_col_Ht, s); }
-void row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn) {
-    DISPATCH_NW(c, c->plan.row_waves, launch_row_update, s, xc, xn);
+void col_H(deblur_ctx* c, hipStream_t s, TileRange r) { DISPATCH_NW(c, c->plan.col_waves, launch_col_H, s, r); }
+void row_resid(deblur_ctx* c, hipStream_t s, TileRange r) {
+    DISPATCH_NW(c, c->plan.row_waves, launch_row_resid, s, r);
 }
+void col_Ht(deblur_ctx* c, hipStream_t s, TileRange r) { DISPATCH_NW(c, c->plan.col_waves, launch_col_Ht, s, r); }
+void row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn, TileRange r) {
+    DISPATCH_NW(c, c->plan.row_waves, launch_row_update, s, xc, xn, r);
+}
+void col_H(deblur_ctx* c, hipStream_t s) { col_H(c, s, all_tiles(c)); }
+void row_resid(deblur_ctx* c, hipStream_t s) { row_resid(c, s, all_tiles(c)); }
+void col_Ht(deblur_ctx* c, hipStream_t s) { col_Ht(c, s, all_tiles(c)); }
+void row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn) { row_update(c, s, xc, xn, all_tiles(c)); }
 
 int waves_hi(int N) { return N == 160 ? dbl::waves_hi<160>() : dbl::waves_hi<320>(); }
 int waves_lo(int N) { return waves_hi(N) / 2; }
@@ -326,12 +348,36 @@ dim3 frame_grid(const deblur_ctx* c) {
     return dim3(std::min(per, 64), c->nt);
 }
 
-// One Local-Solver step on every tile: x[cur] -> x[1 - cur].
-void inner_step(deblur_ctx* c, hipStream_t s, int parity) {
-    col_H(c, s);
-    row_resid(c, s);
-    col_Ht(c, s);
-    row_update(c, s, c->x[parity], c->x[1 - parity]);
+// One Local-Solver step on the tiles of r: x[cur] -> x[1 - cur].
+void inner_step(deblur_ctx* c, hipStream_t s, int parity, TileRange r) {
+    col_H(c, s, r);
+    row_resid(c, s, r);
+    col_Ht(c, s, r);
+    row_update(c, s, c->x[parity], c->x[1 - parity], r);
+}
+void inner_step(deblur_ctx* c, hipStream_t s, int parity) { inner_step(c, s, parity, all_tiles(c)); }
+
+// n Local-Solver steps on every tile starting from x[parity].  With two tile
+// groups the halves run as two independent chains, on s and on aux (forked
+// and joined with events; under graph capture this makes two branches).
+hipError_t local_steps(deblur_ctx* c, hipStream_t s, hipStream_t aux, int n, int parity) {
+    if (n == 0) return hipSuccess;
+    if (c->plan.tile_groups != 2 || c->nt < 2) {
+        for (int i = 0; i < n; ++i, parity = 1 - parity) inner_step(c, s, parity);
+        return hipGetLastError();
+    }
+    hipError_t e = hipEventRecord(c->ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(aux, c->ev_fork, 0);
+    if (e != hipSuccess) return e;
+    const TileRange g0 = tile_group(c, 0), g1 = tile_group(c, 1);
+    for (int i = 0, p = parity; i < n; ++i, p = 1 - p) {
+        inner_step(c, s, p, g0);
+        inner_step(c, aux, p, g1);
+    }
+    e = hipEventRecord(c->ev_join, aux);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_join, 0);
+    if (e == hipSuccess) e = hipGetLastError();
+    return e;
 }
 
 void consensus_launch(deblur_ctx* c, hipStream_t s, int parity) {
@@ -380,7 +426,7 @@ int build_layout(deblur_ctx* c, const float* psfs_host) {
         if (!c->N) return fail(nullptr, DEBLUR_E_SHAPE, "tile support larger than the largest frame (640)");
     }
     const int N = c->N;
-    c->plan = deblur_plan{N, waves_hi(N), waves_hi(N), DEBLUR_ORDER_COLUMN_MAJOR, 0.f};
+    c->plan = deblur_plan{N, waves_hi(N), waves_hi(N), DEBLUR_ORDER_COLUMN_MAJOR, 1, 0.f};
     // PSF checks
     for (int i = 0; i < c->nodes * p.P * p.P; ++i)
         if (!std::isfinite(psfs_host[i])) return fail(nullptr, DEBLUR_E_ARG, "non-finite PSF value");
@@ -550,10 +596,18 @@ int upload_tables(deblur_ctx* c, const float* psfs_host) {
     std::stable_sort(phv.begin(), phv.end(), [&](int a, int b) {
         return c->desc[a].n_terms > c->desc[b].n_terms;
     });
+    // the same within each of the two tile groups [0, ceil(T/2)) and the rest
+    std::vector<int> ph2(pid);
+    const int half = (c->nt + 1) / 2;
+    auto by_terms = [&](int a, int b) { return c->desc[a].n_terms > c->desc[b].n_terms; };
+    std::stable_sort(ph2.begin(), ph2.begin() + half, by_terms);
+    std::stable_sort(ph2.begin() + half, ph2.end(), by_terms);
     if ((rc = dev_alloc(c, &c->perm_id, c->nt))) return rc;
     if ((rc = dev_alloc(c, &c->perm_heavy, c->nt))) return rc;
+    if ((rc = dev_alloc(c, &c->perm_heavy2, c->nt))) return rc;
     HIP_TRY(c, hipMemcpy(c->perm_id, pid.data(), c->nt * 4, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->perm_heavy, phv.data(), c->nt * 4, hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->perm_heavy2, ph2.data(), c->nt * 4, hipMemcpyHostToDevice));
     if ((rc = dev_alloc(c, &c->pd_support, pds.size()))) return rc;
     if ((rc = dev_alloc(c, &c->pd_block, pdb.size()))) return rc;
     if ((rc = make_twiddles(c, c->stream))) return rc;
@@ -665,13 +719,10 @@ int ensure_graph(deblur_ctx* c, int n_inner, int parity, hipGraphExec_t* out) {
     }
     hipGraph_t g = nullptr;
     HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-    int par = parity;
-    for (int i = 0; i < n_inner; ++i) {
-        inner_step(c, c->cap_stream, par);
-        par = 1 - par;
-    }
+    hipError_t e1 = local_steps(c, c->cap_stream, c->cap_aux, n_inner, parity);
+    const int par = (n_inner & 1) ? 1 - parity : parity;
     consensus_launch(c, c->cap_stream, par);
-    hipError_t e1 = hipGetLastError();
+    if (e1 == hipSuccess) e1 = hipGetLastError();
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     if (e1 != hipSuccess || e2 != hipSuccess)
         return fail(c, DEBLUR_E_HIP, std::string("graph capture: ") + hipGetErrorString(e1 != hipSuccess ? e1 : e2));
@@ -708,7 +759,12 @@ void deblur_destroy(deblur_ctx* c) {
     drop_graphs(c);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+    if (c->aux_stream) (void)hipStreamSynchronize(c->aux_stream);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->cap_aux) (void)hipStreamDestroy(c->cap_aux);
+    if (c->aux_stream) (void)hipStreamDestroy(c->aux_stream);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     delete c;
 }
 
@@ -730,9 +786,13 @@ int deblur_create(const deblur_params* params, const float* psfs_host, void* str
         delete c;
         return rc;
     }
-    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-        delete c;
-        return fail(nullptr, DEBLUR_E_HIP, "hipStreamCreate failed");
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->cap_aux, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+        deblur_destroy(c);
+        return fail(nullptr, DEBLUR_E_HIP, "hipStreamCreate / hipEventCreate failed");
     }
     rc = upload_tables(c, psfs_host);
     if (!rc) rc = alloc_state(c);
@@ -842,10 +902,9 @@ int deblur_init(deblur_ctx* c, int32_t mode, const float* x0) {
 int deblur_solve_tiles(deblur_ctx* c, int32_t n_inner) {
     if (!c || n_inner < 0) return fail(c, DEBLUR_E_ARG, "bad argument");
     if (!c->have_state) return fail(c, DEBLUR_E_STATE, "deblur_init must come first");
-    for (int i = 0; i < n_inner; ++i) {
-        inner_step(c, c->stream, c->cur);
-        c->cur = 1 - c->cur;
-    }
+    const hipError_t e = local_steps(c, c->stream, c->aux_stream, n_inner, c->cur);
+    if (e != hipSuccess) return fail(c, DEBLUR_E_HIP, std::string("solve_tiles: ") + hipGetErrorString(e));
+    if (n_inner & 1) c->cur = 1 - c->cur;
     return check_launch(c, "solve_tiles");
 }
 
@@ -1051,7 +1110,9 @@ int deblur_set_plan(deblur_ctx* c, const deblur_plan* pl) {
                     "waves per workgroup must be " + std::to_string(lo) + " or " + std::to_string(hi));
     if (pl->tile_order < DEBLUR_ORDER_COLUMN_MAJOR || pl->tile_order > DEBLUR_ORDER_HEAVY_FIRST)
         return fail(c, DEBLUR_E_ARG, "unknown tile order");
+    if (pl->tile_groups != 1 && pl->tile_groups != 2) return fail(c, DEBLUR_E_ARG, "tile_groups must be 1 or 2");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->aux_stream));
     drop_graphs(c);
     c->plan = *pl;
     c->plan.frame = c->N;
@@ -1117,11 +1178,13 @@ int deblur_autotune(const deblur_params* params, const float* psfs_host, void* s
         rc = deblur_set_observation(c, y, nullptr);
         if (!rc) rc = deblur_init(c, DEBLUR_INIT_OBSERVED, nullptr);
         const int lo = waves_lo(c->N), hi = waves_hi(c->N);
+        for (int groups : {1, 2})
         for (int cw : {hi, lo})
             for (int rw : {hi, lo})
                 for (int order : {DEBLUR_ORDER_COLUMN_MAJOR, DEBLUR_ORDER_TILE_MAJOR, DEBLUR_ORDER_HEAVY_FIRST}) {
                     if (rc) break;
-                    deblur_plan pl{c->N, cw, rw, order, 0.f};
+                    if (groups == 2 && c->nt < 2) break;
+                    deblur_plan pl{c->N, cw, rw, order, groups, 0.f};
                     rc = deblur_set_plan(c, &pl);
                     if (!rc) rc = deblur_run(c, 1, n_inner, 0.0, nullptr, nullptr);   // capture + warm
                     if (rc) break;
@@ -1161,7 +1224,7 @@ int deblur_debug_fft(int32_t n, int32_t batch, int32_t which, const float* in, f
     deblur_ctx tmp;
     tmp.N = n;
     tmp.nt = batch;
-    tmp.plan = deblur_plan{n, waves_hi(n), waves_hi(n), DEBLUR_ORDER_COLUMN_MAJOR, 0.f};
+    tmp.plan = deblur_plan{n, waves_hi(n), waves_hi(n), DEBLUR_ORDER_COLUMN_MAJOR, 1, 0.f};
     std::vector<TileInfo> ti(batch);
     for (int t = 0; t < batch; ++t) {
         ti[t] = TileInfo{};

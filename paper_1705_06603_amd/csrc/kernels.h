@@ -667,13 +667,13 @@ __device__ __forceinline__ float block_sum(float v, float* red, int tid) {
 template <int N, int WV>
 __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_resid(const float2* __restrict__ Yc, const float2* __restrict__ yw,
                                                           const float2* __restrict__ twg, float2* __restrict__ Rr,
-                                                          float* __restrict__ obj_part) {
+                                                          float* __restrict__ obj_part, int t0) {
     using C = Cfg<N, WV>;
     constexpr int n = C::n;
     __shared__ float2 sbuf[C::RB * C::LSR + kLinePad];
     __shared__ float2 tw[C::TWR];
     __shared__ float red[C::W];
-    const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
+    const int t = t0 + blockIdx.y, i0 = blockIdx.x * C::RB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_twiddles<N, WV, false>(tw, twg, tid);
     __syncthreads();
@@ -735,7 +735,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
         const float2* __restrict__ Gk, const float* __restrict__ xc, const float* __restrict__ u,
         const TileInfo* __restrict__ tiles, const float* __restrict__ tentX, const float* __restrict__ omY,
         const float* __restrict__ omX, const float* __restrict__ tau, SolveParams P,
-        const float2* __restrict__ twg, float* __restrict__ xn, float2* __restrict__ Zk) {
+        const float2* __restrict__ twg, float* __restrict__ xn, float2* __restrict__ Zk, int t0) {
     using C = Cfg<N, WV>;
     constexpr int n = C::n;
     static_assert(C::RB * N * sizeof(float) <= C::RB * C::LSR * sizeof(float2), "LDS view too small");
@@ -743,7 +743,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
     __shared__ float2 sbuf[C::RB * C::LSR + kLinePad];
     __shared__ float2 tw[C::TWR];
     float* sg = reinterpret_cast<float*>(sbuf);   // [RB][N] natural view
-    const int t = blockIdx.y, i0 = blockIdx.x * C::RB;
+    const int t = t0 + blockIdx.y, i0 = blockIdx.x * C::RB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     load_twiddles<N, WV, false>(tw, twg, tid);
     const TileInfo ti = tiles[t];
