@@ -222,12 +222,12 @@ int deblur_time_kernels(deblur_ctx* ctx, int32_t reps, float* ms_host);
  *               DEBLUR_ORDER_HEAVY_FIRST   column-group-major over the tiles
  *                                          sorted by PSF term count, most
  *                                          first.
- *   tile_groups 1: every kernel launch covers all tiles; 2: the tiles are
- *               split into two groups (the first ceil(T/2) tiles and the
- *               rest) whose Local-Solver steps run as two independent chains
- *               of launches on two streams, joined before each consensus
- *               step (two branches of the captured graph), so the kernels of
- *               one group fill the GPU while the other's drain.
+ *   tile_groups 1: every kernel launch covers all tiles; 2 or 4: the tiles
+ *               are split into that many contiguous groups (sizes differing
+ *               by at most one) whose Local-Solver steps run as independent
+ *               chains of launches on their own streams, joined before each
+ *               consensus step (branches of the captured graph), so the
+ *               kernels of one group fill the GPU while another's drain.
  * The iterates are bitwise identical under every plan: each pixel goes
  * through the same operations in the same order.  Only the grouping of the
  * partial sums of deblur_objective follows row_waves. */

@@ -26,6 +26,7 @@ thread_local std::string g_create_error;
 
 constexpr int kFrames[3] = {160, 320, 640};
 constexpr int kResCap = 4096;
+constexpr int kMaxGroups = 4;   // tile groups of a launch plan (concurrent branches)
 
 // One axis of the tiling and of the PSF grid (Section III-A, Fig. 1).
 struct Axis {
@@ -158,10 +159,10 @@ struct deblur_ctx {
     deblur_plan plan{};
     int* perm_id = nullptr;      // tile order tables of the column kernels
     int* perm_heavy = nullptr;   // all tiles by term count
-    int* perm_heavy2 = nullptr;  // each half of the tiles by term count (two tile groups)
-    hipStream_t aux_stream = nullptr;   // second branch of a round with two tile groups
-    hipStream_t cap_aux = nullptr;      // its counterpart during graph capture
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int* perm_heavy_g[kMaxGroups + 1] = {};   // [G]: each of G tile groups by term count
+    hipStream_t aux_stream[kMaxGroups - 1] = {};   // further branches of a round with G > 1 tile groups
+    hipStream_t cap_aux[kMaxGroups - 1] = {};      // their counterparts during graph capture
+    hipEvent_t ev_fork = nullptr, ev_join[kMaxGroups - 1] = {};
 };
 
 namespace {
@@ -227,11 +228,18 @@ struct TileRange {
 TileRange all_tiles(const deblur_ctx* c) {
     return {0, c->nt, c->plan.tile_order == DEBLUR_ORDER_HEAVY_FIRST ? c->perm_heavy : c->perm_id};
 }
-// Tile group g of two: the first ceil(T/2) tiles or the rest.
+// Tile group g of G: contiguous ranges of tiles, the first T mod G of them
+// one tile longer.
+void group_bounds(int nt, int G, int g, int& t0, int& cnt) {
+    const int q = nt / G, r = nt % G;
+    t0 = g * q + std::min(g, r);
+    cnt = q + (g < r ? 1 : 0);
+}
 TileRange tile_group(const deblur_ctx* c, int g) {
-    const int h = (c->nt + 1) / 2;
-    const int t0 = g ? h : 0, cnt = g ? c->nt - h : h;
-    return {t0, cnt, (c->plan.tile_order == DEBLUR_ORDER_HEAVY_FIRST ? c->perm_heavy2 : c->perm_id) + t0};
+    const int G = c->plan.tile_groups;
+    int t0, cnt;
+    group_bounds(c->nt, G, g, t0, cnt);
+    return {t0, cnt, (c->plan.tile_order == DEBLUR_ORDER_HEAVY_FIRST ? c->perm_heavy_g[G] : c->perm_id) + t0};
 }
 template <int N, int WV>
 void launch_col_H(deblur_ctx* c, hipStream_t s, TileRange r) {
@@ -357,25 +365,28 @@ void inner_step(deblur_ctx* c, hipStream_t s, int parity, TileRange r) {
 }
 void inner_step(deblur_ctx* c, hipStream_t s, int parity) { inner_step(c, s, parity, all_tiles(c)); }
 
-// n Local-Solver steps on every tile starting from x[parity].  With two tile
-// groups the halves run as two independent chains, on s and on aux (forked
-// and joined with events; under graph capture this makes two branches).
-hipError_t local_steps(deblur_ctx* c, hipStream_t s, hipStream_t aux, int n, int parity) {
+// n Local-Solver steps on every tile starting from x[parity].  With G > 1
+// tile groups the groups run as G independent chains, on s and on aux[0 ..
+// G-2] (forked and joined with events; under graph capture this makes G
+// branches).
+hipError_t local_steps(deblur_ctx* c, hipStream_t s, hipStream_t* aux, int n, int parity) {
     if (n == 0) return hipSuccess;
-    if (c->plan.tile_groups != 2 || c->nt < 2) {
+    const int G = std::min(c->plan.tile_groups, c->nt);
+    if (G <= 1) {
         for (int i = 0; i < n; ++i, parity = 1 - parity) inner_step(c, s, parity);
         return hipGetLastError();
     }
     hipError_t e = hipEventRecord(c->ev_fork, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(aux, c->ev_fork, 0);
+    for (int g = 1; g < G && e == hipSuccess; ++g) e = hipStreamWaitEvent(aux[g - 1], c->ev_fork, 0);
     if (e != hipSuccess) return e;
-    const TileRange g0 = tile_group(c, 0), g1 = tile_group(c, 1);
-    for (int i = 0, p = parity; i < n; ++i, p = 1 - p) {
-        inner_step(c, s, p, g0);
-        inner_step(c, aux, p, g1);
+    TileRange rg[kMaxGroups];
+    for (int g = 0; g < G; ++g) rg[g] = tile_group(c, g);
+    for (int i = 0, p = parity; i < n; ++i, p = 1 - p)
+        for (int g = 0; g < G; ++g) inner_step(c, g ? aux[g - 1] : s, p, rg[g]);
+    for (int g = 1; g < G && e == hipSuccess; ++g) {
+        e = hipEventRecord(c->ev_join[g - 1], aux[g - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_join[g - 1], 0);
     }
-    e = hipEventRecord(c->ev_join, aux);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_join, 0);
     if (e == hipSuccess) e = hipGetLastError();
     return e;
 }
@@ -596,18 +607,23 @@ int upload_tables(deblur_ctx* c, const float* psfs_host) {
     std::stable_sort(phv.begin(), phv.end(), [&](int a, int b) {
         return c->desc[a].n_terms > c->desc[b].n_terms;
     });
-    // the same within each of the two tile groups [0, ceil(T/2)) and the rest
-    std::vector<int> ph2(pid);
-    const int half = (c->nt + 1) / 2;
-    auto by_terms = [&](int a, int b) { return c->desc[a].n_terms > c->desc[b].n_terms; };
-    std::stable_sort(ph2.begin(), ph2.begin() + half, by_terms);
-    std::stable_sort(ph2.begin() + half, ph2.end(), by_terms);
     if ((rc = dev_alloc(c, &c->perm_id, c->nt))) return rc;
     if ((rc = dev_alloc(c, &c->perm_heavy, c->nt))) return rc;
-    if ((rc = dev_alloc(c, &c->perm_heavy2, c->nt))) return rc;
     HIP_TRY(c, hipMemcpy(c->perm_id, pid.data(), c->nt * 4, hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->perm_heavy, phv.data(), c->nt * 4, hipMemcpyHostToDevice));
-    HIP_TRY(c, hipMemcpy(c->perm_heavy2, ph2.data(), c->nt * 4, hipMemcpyHostToDevice));
+    // the same order within each group of a split into G tile groups
+    c->perm_heavy_g[1] = c->perm_heavy;
+    for (int G = 2; G <= kMaxGroups; ++G) {
+        std::vector<int> pg(pid);
+        for (int g = 0; g < G; ++g) {
+            int t0, cnt;
+            group_bounds(c->nt, G, g, t0, cnt);
+            std::stable_sort(pg.begin() + t0, pg.begin() + t0 + cnt,
+                             [&](int a, int b) { return c->desc[a].n_terms > c->desc[b].n_terms; });
+        }
+        if ((rc = dev_alloc(c, &c->perm_heavy_g[G], c->nt))) return rc;
+        HIP_TRY(c, hipMemcpy(c->perm_heavy_g[G], pg.data(), c->nt * 4, hipMemcpyHostToDevice));
+    }
     if ((rc = dev_alloc(c, &c->pd_support, pds.size()))) return rc;
     if ((rc = dev_alloc(c, &c->pd_block, pdb.size()))) return rc;
     if ((rc = make_twiddles(c, c->stream))) return rc;
@@ -759,12 +775,15 @@ void deblur_destroy(deblur_ctx* c) {
     drop_graphs(c);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
-    if (c->aux_stream) (void)hipStreamSynchronize(c->aux_stream);
+    for (hipStream_t a : c->aux_stream)
+        if (a) (void)hipStreamSynchronize(a);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    if (c->cap_aux) (void)hipStreamDestroy(c->cap_aux);
-    if (c->aux_stream) (void)hipStreamDestroy(c->aux_stream);
+    for (int g = 0; g < kMaxGroups - 1; ++g) {
+        if (c->cap_aux[g]) (void)hipStreamDestroy(c->cap_aux[g]);
+        if (c->aux_stream[g]) (void)hipStreamDestroy(c->aux_stream[g]);
+        if (c->ev_join[g]) (void)hipEventDestroy(c->ev_join[g]);
+    }
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     delete c;
 }
 
@@ -786,11 +805,13 @@ int deblur_create(const deblur_params* params, const float* psfs_host, void* str
         delete c;
         return rc;
     }
-    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->cap_aux, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    bool ok = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (int g = 0; ok && g < kMaxGroups - 1; ++g)
+        ok = hipStreamCreateWithFlags(&c->cap_aux[g], hipStreamNonBlocking) == hipSuccess &&
+             hipStreamCreateWithFlags(&c->aux_stream[g], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&c->ev_join[g], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
         deblur_destroy(c);
         return fail(nullptr, DEBLUR_E_HIP, "hipStreamCreate / hipEventCreate failed");
     }
@@ -1110,9 +1131,10 @@ int deblur_set_plan(deblur_ctx* c, const deblur_plan* pl) {
                     "waves per workgroup must be " + std::to_string(lo) + " or " + std::to_string(hi));
     if (pl->tile_order < DEBLUR_ORDER_COLUMN_MAJOR || pl->tile_order > DEBLUR_ORDER_HEAVY_FIRST)
         return fail(c, DEBLUR_E_ARG, "unknown tile order");
-    if (pl->tile_groups != 1 && pl->tile_groups != 2) return fail(c, DEBLUR_E_ARG, "tile_groups must be 1 or 2");
+    if (pl->tile_groups != 1 && pl->tile_groups != 2 && pl->tile_groups != 4)
+        return fail(c, DEBLUR_E_ARG, "tile_groups must be 1, 2 or 4");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->aux_stream));
+    for (hipStream_t a : c->aux_stream) HIP_TRY(c, hipStreamSynchronize(a));
     drop_graphs(c);
     c->plan = *pl;
     c->plan.frame = c->N;
@@ -1178,12 +1200,12 @@ int deblur_autotune(const deblur_params* params, const float* psfs_host, void* s
         rc = deblur_set_observation(c, y, nullptr);
         if (!rc) rc = deblur_init(c, DEBLUR_INIT_OBSERVED, nullptr);
         const int lo = waves_lo(c->N), hi = waves_hi(c->N);
-        for (int groups : {1, 2})
+        for (int groups : {1, 2, 4})
         for (int cw : {hi, lo})
             for (int rw : {hi, lo})
                 for (int order : {DEBLUR_ORDER_COLUMN_MAJOR, DEBLUR_ORDER_TILE_MAJOR, DEBLUR_ORDER_HEAVY_FIRST}) {
                     if (rc) break;
-                    if (groups == 2 && c->nt < 2) break;
+                    if (groups > c->nt) break;
                     deblur_plan pl{c->N, cw, rw, order, groups, 0.f};
                     rc = deblur_set_plan(c, &pl);
                     if (!rc) rc = deblur_run(c, 1, n_inner, 0.0, nullptr, nullptr);   // capture + warm
