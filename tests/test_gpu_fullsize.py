@@ -39,11 +39,13 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _one_round_map(name, frame, sampled, rounds_before):
+def _one_round_map(name, frame, sampled, rounds_before, plan=None):
     """One-step map parity: the GPU state after ``rounds_before`` graph-captured
     D-R rounds is fed to the FP64 oracle, which runs one more round (n_inner
     Local-Solver steps + consensus + dual update, Algorithm 1) on the sampled
-    tiles and their neighbours; the GPU's next state must agree."""
+    tiles and their neighbours; the GPU's next state must agree.  ``plan``
+    (launch-plan fields) selects the launch shapes, as the benchmark's
+    autotuner does."""
     import torch
     from paper_1705_06603_amd import _lib as dl
     w = workloads.WORKLOADS[name]
@@ -67,6 +69,8 @@ def _one_round_map(name, frame, sampled, rounds_before):
                             gamma=w.gamma, rho=w.rho)
     ctx = dl.Context(params, psfs)
     assert ctx.tiles[0].frame == frame
+    if plan:
+        ctx.set_plan(**plan)
     ctx.set_observation(torch.tensor(y.astype(np.float32), device="cuda"),
                         torch.tensor(W.astype(np.float32), device="cuda"))
     ctx.init()
@@ -104,12 +108,16 @@ def test_batched_workload_one_round_map_on_sampled_tiles():
     """2048 x 2048, 8 x 8 tiles, 31 x 31 Moffat grid, frame 320; corner, edge,
     interior and far-corner tiles, first round and a later round."""
     _one_round_map("batched", 320, [0, 3, 4 * 8 + 5, 63], 0)
-    _one_round_map("batched", 320, [0, 4 * 8 + 5], 3)
+    # launch shapes the autotuner picks for this workload: 2-wave workgroups,
+    # two or four concurrent tile groups
+    _one_round_map("batched", 320, [0, 4 * 8 + 5], 3,
+                   plan=dict(col_waves=2, row_waves=2, tile_order=2, tile_groups=2))
+    _one_round_map("batched", 320, [3, 63], 1, plan=dict(col_waves=2, row_waves=2, tile_order=0, tile_groups=4))
 
 
 def test_large_workload_one_round_map_on_sampled_tiles():
     """8192 x 8192, 16 x 16 tiles of 512-576 px, 63 x 63 Moffat grid, frame 640."""
-    _one_round_map("large", 640, [0, 16 * 8 + 9, 255], 2)
+    _one_round_map("large", 640, [0, 16 * 8 + 9, 255], 2, plan=dict(tile_groups=4))
 
 
 def test_combined_workload_one_round_map_on_sampled_tiles():
