@@ -5,9 +5,9 @@
 // of radix-R passes (R in {20, 5, 4, 2}; each divides 20, so every lane does
 // 20/R butterflies per pass and no lane idles).  A radix-20 pass is one
 // length-20 DFT per lane done in registers (4 x 5 with constant twiddles),
-// which saves one LDS exchange over separate radix-5 and radix-4 passes.  Between passes the
-// values go through the wave's private LDS region; waves never wait on each
-// other, only on their own LDS traffic (wave_sync).
+// which saves one LDS exchange over separate radix-5 and radix-4 passes.
+// Between passes the values go through the wave's private LDS region; waves
+// never wait on each other, only on their own LDS traffic (wave_sync).
 //
 // Pass p with radix R after sub-length Ns (Stockham autosort, decimation in
 // time): butterfly j of a line reads elements j + r n/R, multiplies element r

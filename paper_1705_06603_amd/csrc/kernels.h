@@ -113,31 +113,6 @@ __device__ __forceinline__ void store_spectrum_T(const float2* __restrict__ sbuf
     }
 }
 
-// Transposed load of packed half-spectra in[f][i0 + row] into sbuf[row][f].
-// All global loads of a thread are issued before any LDS store, so their
-// latencies overlap instead of being paid once per unrolled group.
-template <int N, int WV>
-__device__ __forceinline__ void load_spectrum_T(float2* __restrict__ sbuf, const float2* __restrict__ in,
-                                                int i0, int tid) {
-    using C = Cfg<N, WV>;
-    constexpr int n = C::n;
-    constexpr int PER = C::RB * n / C::NT;
-    static_assert(PER * C::NT == C::RB * n, "transpose does not divide the workgroup");
-    float2 buf[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int e = tid + k * C::NT;
-        const int row = e % C::RB, f = e / C::RB;
-        buf[k] = in[(size_t)f * N + i0 + row];
-    }
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int e = tid + k * C::NT;
-        const int row = e % C::RB, f = e / C::RB;
-        sbuf[line_off<n>(row) + f] = buf[k];
-    }
-}
-
 // Transposed load of packed half-spectra for a row C2R: reads the pair
 // (f, n - f) of each row from in[.][i0 + row] and stores the complex
 // sequence Z = E + i O whose inverse length-n FFT gives (x[2m], x[2m+1]):
@@ -190,7 +165,7 @@ __device__ __forceinline__ void load_c2r_T(float2* __restrict__ sbuf, const floa
 }
 
 // Wave-level inverse row FFT of the wave's rows (Z from load_c2r_T).
-// Result: v[s] = (x[2m], x[2m+1]) in layout L5 of length n, times N/2
+// Result: v[s] = (x[2m], x[2m+1]) in the natural layout of length n, times N/2
 // relative to the normalised inverse (folded into the spectra).
 template <int N>
 __device__ __forceinline__ void row_c2r_ready(float2 (&v)[kV], float2* __restrict__ sw,
@@ -208,35 +183,7 @@ __device__ __forceinline__ void row_c2r_ready(float2 (&v)[kV], float2* __restric
     fft_passes<n, kInv>(v, sw, tw + C::TWR_F, lane);
 }
 
-// Wave-level C2R of the wave's rows held in sw (packed half-spectra, natural
-// order).  Result: v[s] = (x[2m], x[2m+1]) in layout L5 of length n, i.e.
-// times N/2 relative to the normalised inverse (folded into the spectra).
-template <int N>
-__device__ __forceinline__ void row_c2r_wave(float2 (&v)[kV], float2* __restrict__ sw,
-                                             const float2* __restrict__ tw, int lane) {
-    using C = Cfg<N>;
-    constexpr int n = C::n;
-    constexpr int R0 = first_radix<n, kInv>();
-#pragma unroll
-    for (int s = 0; s < kV; ++s) {
-        int q, f;
-        slot_pos<n, R0>(lane, s, q, f);
-        const float2 X = sw[line_off<n>(q) + f];
-        if (f == 0) {
-            v[s] = make_float2(0.5f * (X.x + X.y), 0.5f * (X.x - X.y));
-        } else {
-            const float2 Xm = sw[line_off<n>(q) + (n - f)];
-            const float2 E = make_float2(0.5f * (X.x + Xm.x), 0.5f * (X.y - Xm.y));
-            const float2 D = make_float2(0.5f * (X.x - Xm.x), 0.5f * (X.y + Xm.y));
-            const float2 O = cmulc(D, tw[C::RPOST + f]);   // D * W_N^{-f}
-            v[s] = make_float2(E.x - O.y, E.y + O.x);   // E + i O
-        }
-    }
-    wave_sync();
-    fft_passes<n, kInv>(v, sw, tw + C::TWR_F, lane);
-}
-
-// Wave-level forward row FFT of v (layout L5 of length n, packed real pairs)
+// Wave-level forward row FFT of v (natural layout of length n, packed real pairs)
 // into sw in natural order.
 template <int N>
 __device__ __forceinline__ void row_fft_wave(float2 (&v)[kV], float2* __restrict__ sw,
