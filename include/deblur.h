@@ -306,6 +306,13 @@ typedef struct deblur_cnn deblur_cnn;
  * initialisation (last layer scaled by 0.1).  stream as for deblur_create. */
 int deblur_cnn_create(const float* params_host, int32_t seed, int32_t max_batch, int32_t max_h, int32_t max_w,
                       void* stream, deblur_cnn** out);
+/* The same with forward buffers only (activations of three layers and the
+ * output: 3 * 64 + 4 bytes per pixel of max_batch x max_h x max_w), for
+ * warm-starting many large tiles in one launch per layer; loss_grad and
+ * train_step return DEBLUR_E_STATE on it.  Weights come from params_host
+ * (e.g. deblur_cnn_get_params of a trained network). */
+int deblur_cnn_create_inference(const float* params_host, int32_t seed, int32_t max_batch, int32_t max_h,
+                                int32_t max_w, void* stream, deblur_cnn** out);
 void deblur_cnn_destroy(deblur_cnn* net);
 const char* deblur_cnn_last_error(const deblur_cnn* net);
 int deblur_cnn_get_params(deblur_cnn* net, float* params_host);

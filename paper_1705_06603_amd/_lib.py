@@ -105,6 +105,7 @@ def lib():
         "deblur_time_kernels": ([vp, i32, ctypes.POINTER(ctypes.c_float)], i32),
         "deblur_debug_fft": ([i32, i32, i32, f32p, f32p, vp], i32),
         "deblur_cnn_create": ([vp, i32, i32, i32, i32, vp, ctypes.POINTER(vp)], i32),
+        "deblur_cnn_create_inference": ([vp, i32, i32, i32, i32, vp, ctypes.POINTER(vp)], i32),
         "deblur_cnn_destroy": ([vp], None),
         "deblur_cnn_last_error": ([vp], ctypes.c_char_p),
         "deblur_cnn_get_params": ([vp, vp], i32),
@@ -136,7 +137,7 @@ def exported_symbols():
         "deblur_solve_tiles", "deblur_consensus", "deblur_run", "deblur_get_state",
         "deblur_set_state", "deblur_assemble", "deblur_objective", "deblur_step_sizes",
         "deblur_blur_global", "deblur_time_kernels", "deblur_debug_fft",
-        "deblur_cnn_create", "deblur_cnn_destroy", "deblur_cnn_last_error", "deblur_cnn_get_params",
+        "deblur_cnn_create", "deblur_cnn_create_inference", "deblur_cnn_destroy", "deblur_cnn_last_error", "deblur_cnn_get_params",
         "deblur_cnn_set_params", "deblur_cnn_forward", "deblur_cnn_loss_grad", "deblur_cnn_train_step",
         "deblur_cnn_time_forward", "deblur_init_cnn", "deblur_warm_inputs",
         "deblur_get_plan", "deblur_set_plan", "deblur_autotune",
@@ -384,7 +385,7 @@ N_CNN_PARAMS = 19105
 class Net:
     """The warm-start network on the GPU (weights, Adam state, buffers)."""
 
-    def __init__(self, max_batch, max_h, max_w, params=None, seed=0, stream=None):
+    def __init__(self, max_batch, max_h, max_w, params=None, seed=0, stream=None, inference_only=False):
         import torch
         self._torch = torch
         self._L = lib()
@@ -394,8 +395,9 @@ class Net:
             p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
             if p.size != N_CNN_PARAMS:
                 raise ValueError("expected 19105 parameters")
-        rc = self._L.deblur_cnn_create(p.ctypes.data_as(ctypes.c_void_p) if p is not None else None, seed,
-                                       max_batch, max_h, max_w, _stream_handle(stream), ctypes.byref(h))
+        create = self._L.deblur_cnn_create_inference if inference_only else self._L.deblur_cnn_create
+        rc = create(p.ctypes.data_as(ctypes.c_void_p) if p is not None else None, seed,
+                    max_batch, max_h, max_w, _stream_handle(stream), ctypes.byref(h))
         if rc != 0:
             raise DeblurError(rc, self._L.deblur_cnn_last_error(None).decode())
         self._h = h

@@ -1290,6 +1290,7 @@ int deblur_debug_fft(int32_t n, int32_t batch, int32_t which, const float* in, f
 struct deblur_cnn {
     hipStream_t stream = nullptr;
     int maxB = 0, maxH = 0, maxW = 0;
+    bool trainable = true;   // false: forward buffers only (deblur_cnn_create_inference)
     std::string err;
     float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
     unsigned short *wf2 = nullptr, *wb2 = nullptr, *wf3 = nullptr, *wb3 = nullptr;
@@ -1449,11 +1450,12 @@ int net_shape_ok(deblur_cnn* n, int B, int H, int W) {
 
 extern "C" {
 
-int deblur_cnn_create(const float* params, int32_t seed, int32_t maxB, int32_t maxH, int32_t maxW, void* stream,
-                      deblur_cnn** out) {
+static int cnn_create(const float* params, int32_t seed, int32_t maxB, int32_t maxH, int32_t maxW, void* stream,
+                      bool trainable, deblur_cnn** out) {
     if (!out || maxB < 1 || maxH < 8 || maxW < 32) return cfail(nullptr, DEBLUR_E_ARG, "bad argument");
     *out = nullptr;
     deblur_cnn* n = new deblur_cnn();
+    n->trainable = trainable;
     n->stream = static_cast<hipStream_t>(stream);
     n->maxB = maxB;
     n->maxH = maxH;
@@ -1477,14 +1479,16 @@ int deblur_cnn_create(const float* params, int32_t seed, int32_t maxB, int32_t m
     if (!rc) rc = net_alloc(n, &n->a1, px * K::C);
     if (!rc) rc = net_alloc(n, &n->a2, px * K::C);
     if (!rc) rc = net_alloc(n, &n->a3, px * K::C);
-    if (!rc) rc = net_alloc(n, &n->dpA, px * K::C);
-    if (!rc) rc = net_alloc(n, &n->dpB, px * K::C);
     if (!rc) rc = net_alloc(n, &n->out, px);
-    if (!rc) rc = net_alloc(n, &n->dout, px);
-    if (!rc) rc = net_alloc(n, &n->part, n->max_chunks * ncol);
-    if (!rc) rc = net_alloc(n, &n->red0, ((n->max_chunks + 63) / 64) * ncol);
-    if (!rc) rc = net_alloc(n, &n->red1, ((n->max_chunks + 4095) / 4096 + 1) * ncol);
-    if (!rc) rc = net_alloc(n, &n->loss_part, n->max_loss_parts);
+    if (trainable) {   // backward activations, weight-gradient partials, loss partials
+        if (!rc) rc = net_alloc(n, &n->dpA, px * K::C);
+        if (!rc) rc = net_alloc(n, &n->dpB, px * K::C);
+        if (!rc) rc = net_alloc(n, &n->dout, px);
+        if (!rc) rc = net_alloc(n, &n->part, n->max_chunks * ncol);
+        if (!rc) rc = net_alloc(n, &n->red0, ((n->max_chunks + 63) / 64) * ncol);
+        if (!rc) rc = net_alloc(n, &n->red1, ((n->max_chunks + 4095) / 4096 + 1) * ncol);
+        if (!rc) rc = net_alloc(n, &n->loss_part, n->max_loss_parts);
+    }
     if (rc) {
         g_create_error = n->err;
         for (void* p : n->allocs) (void)hipFree(p);
@@ -1518,6 +1522,16 @@ int deblur_cnn_create(const float* params, int32_t seed, int32_t maxB, int32_t m
     }
     *out = n;
     return DEBLUR_OK;
+}
+
+int deblur_cnn_create(const float* params, int32_t seed, int32_t maxB, int32_t maxH, int32_t maxW, void* stream,
+                      deblur_cnn** out) {
+    return cnn_create(params, seed, maxB, maxH, maxW, stream, true, out);
+}
+
+int deblur_cnn_create_inference(const float* params, int32_t seed, int32_t maxB, int32_t maxH, int32_t maxW,
+                                void* stream, deblur_cnn** out) {
+    return cnn_create(params, seed, maxB, maxH, maxW, stream, false, out);
 }
 
 void deblur_cnn_destroy(deblur_cnn* n) {
@@ -1561,6 +1575,7 @@ int deblur_cnn_forward(deblur_cnn* n, const float* img, const int32_t* valid_hos
 int deblur_cnn_loss_grad(deblur_cnn* n, const float* img, const float* target, int32_t B, int32_t H, int32_t W,
                          double* loss_host, float* grad_host) {
     if (!n || !img || !target) return cfail(n, DEBLUR_E_ARG, "null argument");
+    if (!n->trainable) return cfail(n, DEBLUR_E_STATE, "inference-only network");
     int rc = net_shape_ok(n, B, H, W);
     if (!rc) rc = net_loss_grad(n, img, target, B, H, W, nullptr, loss_host);
     if (rc) return rc;
@@ -1574,6 +1589,7 @@ int deblur_cnn_loss_grad(deblur_cnn* n, const float* img, const float* target, i
 int deblur_cnn_train_step(deblur_cnn* n, const float* img, const float* target, int32_t B, int32_t H, int32_t W,
                           float lr, double* loss_host) {
     if (!n || !img || !target || !(lr > 0.f)) return cfail(n, DEBLUR_E_ARG, "bad argument");
+    if (!n->trainable) return cfail(n, DEBLUR_E_STATE, "inference-only network");
     int rc = net_shape_ok(n, B, H, W);
     if (!rc) rc = net_loss_grad(n, img, target, B, H, W, nullptr, loss_host);
     if (rc) return rc;

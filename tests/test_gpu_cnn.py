@@ -161,3 +161,23 @@ def test_trained_warm_start_gains_over_plain_start():
     print("residuals warm", res_w, "plain", res_p)
     net.close()
     ctx.close()
+
+
+def test_inference_only_network():
+    """Forward buffers only: the same output as a trainable network with the
+    same weights, and training calls are refused."""
+    import torch
+    from paper_1705_06603_amd import _lib as dl
+    flat = _params(4)
+    a = dl.Net(2, 64, 64, params=flat)
+    b = dl.Net(2, 64, 64, params=flat, inference_only=True)
+    rng = np.random.default_rng(6)
+    img = torch.tensor(rng.random((2, 64, 64)).astype(np.float32), device="cuda")
+    oa = a.forward(img, valid=[[64, 64], [40, 50]]).cpu().numpy()
+    ob = b.forward(img, valid=[[64, 64], [40, 50]]).cpu().numpy()
+    assert np.array_equal(oa, ob)
+    with pytest.raises(dl.DeblurError) as e:
+        b.train_step(img, img, 1e-3)
+    assert e.value.code == -5
+    a.close()
+    b.close()
