@@ -184,17 +184,23 @@ def cpu_baseline(scene, psfs, y, W, w, budget_s=20.0):
                       f"one process); whole-image rate extrapolated by tile count"}
 
 
-def run_to_tolerance(ctx, w, tol, max_rounds, label, chunk=100):
+def run_to_tolerance(ctx, w, tol, max_rounds, label, chunk=100, growth=0):
     """D-R rounds until the residual reaches tol (checked every round), in
-    chunks of `chunk` rounds with a progress line after each chunk."""
+    chunks of `chunk` rounds with a progress line after each chunk.  With
+    growth > 0, round k runs n_inner + growth * k Local-Solver steps."""
     res = []
     while len(res) < max_rounds:
-        r = ctx.run(min(chunk, max_rounds - len(res)), w.n_inner, tol=tol)
+        r = ctx.run(min(chunk, max_rounds - len(res)), w.n_inner, tol=tol, growth=growth, first_round=len(res))
         res += r
         print(f"# {label}: {len(res)} rounds, residual {res[-1]:.3e}", file=sys.stderr, flush=True)
         if res[-1] <= tol:
             break
     return res
+
+
+def schedule_iterations(w, rounds, growth):
+    """Local-Solver iterations in the first `rounds` rounds of a schedule."""
+    return sum(w.n_inner + growth * k for k in range(rounds))
 
 
 def convergence(ctx, w, args):
@@ -227,22 +233,27 @@ def convergence(ctx, w, args):
                         "steps": args.train_steps, "batch": 16, "loss_first": losses[0], "loss_last": losses[-1],
                         "seconds": round(train_s, 2)}}
     stream = torch.cuda.current_stream()
-    for label in ("plain", "warm"):
+    # plain and warm start with the fixed schedule; plain start with the
+    # paper's growing schedule (n_inner + n_inner k steps in round k)
+    for label in ("plain", "warm", "plain_growing"):
+        growth = w.n_inner if label == "plain_growing" else 0
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        if label == "plain":
+        if label == "warm":
+            _, nf = ctx.init_cnn(net)
+        else:
             ctx.init()
             nf = None
-        else:
-            _, nf = ctx.init_cnn(net)
-        res = run_to_tolerance(ctx, w, 1e-4, args.max_rounds, label)
+        res = run_to_tolerance(ctx, w, 1e-4, args.max_rounds if not growth else 60, label,
+                               chunk=100 if not growth else 5, growth=growth)
         e1.record(stream)
         torch.cuda.synchronize()
         reached = res[-1] <= 1e-4
-        first = lambda th: next(((i + 1) * w.n_inner for i, r in enumerate(res) if r <= th), None)
-        out[label] = {"reached": bool(reached), "iterations": len(res) * w.n_inner if reached else None,
+        first = lambda th: next((schedule_iterations(w, i + 1, growth) for i, r in enumerate(res) if r <= th), None)
+        out[label] = {"reached": bool(reached),
+                      "iterations": schedule_iterations(w, len(res), growth) if reached else None,
                       "ms": round(e0.elapsed_time(e1), 2) if reached else None,
                       "ms_run": round(e0.elapsed_time(e1), 2), "rounds_run": len(res),
                       "final_residual": res[-1], "iterations_to_1e-3": first(1e-3),

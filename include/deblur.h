@@ -173,6 +173,16 @@ int deblur_consensus(deblur_ctx* ctx, double* residual_host);
 int deblur_run(deblur_ctx* ctx, int32_t n_outer, int32_t n_inner, double tol,
                double* residuals_host, int32_t* rounds_done);
 
+/* Algorithm 1 with the growing inexact schedule of Section IV-B: round k
+ * (k = first_round, first_round + 1, ...) runs n_inner + growth * k
+ * Local-Solver steps, then the consensus step (growth 10 with n_inner 10 is
+ * the paper's 10 + 10k).  growth must be a multiple of n_inner (the rounds
+ * are replays of one captured n_inner-step graph and a consensus graph);
+ * growth = 0 is deblur_run.  first_round lets a caller continue a schedule
+ * over several calls.  tol, residuals_host and rounds_done as deblur_run. */
+int deblur_run_schedule(deblur_ctx* ctx, int32_t n_outer, int32_t n_inner, int32_t growth, int32_t first_round,
+                        double tol, double* residuals_host, int32_t* rounds_done);
+
 /* Checkpoint / restore (x, u), device support-packed arrays. */
 int deblur_get_state(deblur_ctx* ctx, float* x_tiles, float* u_tiles);
 int deblur_set_state(deblur_ctx* ctx, const float* x_tiles, const float* u_tiles);

@@ -96,6 +96,7 @@ def lib():
         "deblur_solve_tiles": ([vp, i32], i32),
         "deblur_consensus": ([vp, dp], i32),
         "deblur_run": ([vp, i32, i32, ctypes.c_double, dp, ctypes.POINTER(i32)], i32),
+        "deblur_run_schedule": ([vp, i32, i32, i32, i32, ctypes.c_double, dp, ctypes.POINTER(i32)], i32),
         "deblur_get_state": ([vp, f32p, f32p], i32),
         "deblur_set_state": ([vp, f32p, f32p], i32),
         "deblur_assemble": ([vp, f32p], i32),
@@ -134,7 +135,7 @@ def exported_symbols():
     return [
         "deblur_create", "deblur_destroy", "deblur_last_error", "deblur_tile_layout",
         "deblur_set_observation", "deblur_apply_H", "deblur_apply_Ht", "deblur_init",
-        "deblur_solve_tiles", "deblur_consensus", "deblur_run", "deblur_get_state",
+        "deblur_solve_tiles", "deblur_consensus", "deblur_run", "deblur_run_schedule", "deblur_get_state",
         "deblur_set_state", "deblur_assemble", "deblur_objective", "deblur_step_sizes",
         "deblur_blur_global", "deblur_time_kernels", "deblur_debug_fft",
         "deblur_cnn_create", "deblur_cnn_create_inference", "deblur_cnn_destroy", "deblur_cnn_last_error", "deblur_cnn_get_params",
@@ -250,10 +251,15 @@ class Context:
         self._check(self._L.deblur_consensus(self._h, ctypes.byref(r)))
         return r.value
 
-    def run(self, n_outer, n_inner=10, tol=0.0):
+    def run(self, n_outer, n_inner=10, tol=0.0, growth=0, first_round=0):
+        """D-R rounds; with growth > 0 round k runs n_inner + growth * k steps."""
         res = (ctypes.c_double * max(n_outer, 1))()
         done = ctypes.c_int32()
-        self._check(self._L.deblur_run(self._h, n_outer, n_inner, tol, res, ctypes.byref(done)))
+        if growth:
+            self._check(self._L.deblur_run_schedule(self._h, n_outer, n_inner, growth, first_round, tol, res,
+                                                    ctypes.byref(done)))
+        else:
+            self._check(self._L.deblur_run(self._h, n_outer, n_inner, tol, res, ctypes.byref(done)))
         return [res[i] for i in range(done.value)]
 
     def get_state(self):

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -153,7 +154,7 @@ struct deblur_ctx {
     double* gmap = nullptr;
     int* use_cnn = nullptr;
     std::vector<void*> allocs;
-    std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;   // (steps, parity, with consensus)
     std::vector<hipGraph_t> graph_defs;
     // launch plan (frame fixed at creation; the rest set by deblur_set_plan)
     deblur_plan plan{};
@@ -726,8 +727,10 @@ int compute_rowsums(deblur_ctx* c) {
     return DEBLUR_OK;
 }
 
-int ensure_graph(deblur_ctx* c, int n_inner, int parity, hipGraphExec_t* out) {
-    auto key = std::make_pair(n_inner, parity);
+// The captured graph of n_inner Local-Solver steps from x[parity], followed
+// by the consensus step when with_consensus (one D-R round); cached per key.
+int ensure_graph(deblur_ctx* c, int n_inner, int parity, bool with_consensus, hipGraphExec_t* out) {
+    const auto key = std::make_tuple(n_inner, parity, with_consensus ? 1 : 0);
     auto it = c->graphs.find(key);
     if (it != c->graphs.end()) {
         *out = it->second;
@@ -737,7 +740,7 @@ int ensure_graph(deblur_ctx* c, int n_inner, int parity, hipGraphExec_t* out) {
     HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = local_steps(c, c->cap_stream, c->cap_aux, n_inner, parity);
     const int par = (n_inner & 1) ? 1 - parity : parity;
-    consensus_launch(c, c->cap_stream, par);
+    if (with_consensus) consensus_launch(c, c->cap_stream, par);
     if (e1 == hipSuccess) e1 = hipGetLastError();
     hipError_t e2 = hipStreamEndCapture(c->cap_stream, &g);
     if (e1 != hipSuccess || e2 != hipSuccess)
@@ -948,8 +951,8 @@ int deblur_run(deblur_ctx* c, int32_t n_outer, int32_t n_inner, double tol, doub
     if (n_outer > kResCap) return fail(c, DEBLUR_E_ARG, "n_outer exceeds 4096");
     if (!c->have_state) return fail(c, DEBLUR_E_STATE, "deblur_init must come first");
     hipGraphExec_t g[2] = {nullptr, nullptr};
-    int rc = ensure_graph(c, n_inner, c->cur, &g[c->cur]);
-    if (!rc && (n_inner & 1)) rc = ensure_graph(c, n_inner, 1 - c->cur, &g[1 - c->cur]);
+    int rc = ensure_graph(c, n_inner, c->cur, true, &g[c->cur]);
+    if (!rc && (n_inner & 1)) rc = ensure_graph(c, n_inner, 1 - c->cur, true, &g[1 - c->cur]);
     if (rc) return rc;
     hipLaunchKernelGGL(dbl::k_set_int, dim3(1), dim3(1), 0, c->stream, c->res_counter, 0);
     int k = 0;
@@ -957,6 +960,54 @@ int deblur_run(deblur_ctx* c, int32_t n_outer, int32_t n_inner, double tol, doub
     for (; k < n_outer;) {
         HIP_TRY(c, hipGraphLaunch(g[c->cur], c->stream));
         if (n_inner & 1) c->cur = 1 - c->cur;
+        ++k;
+        if (tol > 0.0) {
+            HIP_TRY(c, hipMemcpyAsync(c->h_pinned, c->res_last, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            if (!std::isfinite(c->h_pinned[0])) {
+                nonfinite = true;
+                break;
+            }
+            if (c->h_pinned[0] <= tol) break;
+        }
+    }
+    if (residuals && k > 0)
+        HIP_TRY(c, hipMemcpyAsync(residuals, c->res_hist, k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (done) *done = k;
+    if (nonfinite) return fail(c, DEBLUR_E_NONFINITE, "non-finite consensus residual");
+    if (residuals)
+        for (int i = 0; i < k; ++i)
+            if (!std::isfinite(residuals[i])) return fail(c, DEBLUR_E_NONFINITE, "non-finite consensus residual");
+    return DEBLUR_OK;
+}
+
+int deblur_run_schedule(deblur_ctx* c, int32_t n_outer, int32_t n_inner, int32_t growth, int32_t first_round,
+                        double tol, double* residuals, int32_t* done) {
+    if (!c || n_outer < 0 || n_inner < 1 || growth < 0 || first_round < 0)
+        return fail(c, DEBLUR_E_ARG, "bad argument");
+    if (growth % n_inner) return fail(c, DEBLUR_E_ARG, "growth must be a multiple of n_inner");
+    if (growth == 0) return deblur_run(c, n_outer, n_inner, tol, residuals, done);
+    if (n_outer > kResCap) return fail(c, DEBLUR_E_ARG, "n_outer exceeds 4096");
+    if (!c->have_state) return fail(c, DEBLUR_E_STATE, "deblur_init must come first");
+    // one graph of n_inner steps and one of the consensus step alone, per parity
+    hipGraphExec_t steps[2] = {nullptr, nullptr}, cons[2] = {nullptr, nullptr};
+    int rc = 0;
+    for (int p = 0; p < 2 && !rc; ++p) {
+        if ((n_inner & 1) || p == c->cur) rc = ensure_graph(c, n_inner, p, false, &steps[p]);
+        if (!rc) rc = ensure_graph(c, 0, p, true, &cons[p]);
+    }
+    if (rc) return rc;
+    hipLaunchKernelGGL(dbl::k_set_int, dim3(1), dim3(1), 0, c->stream, c->res_counter, 0);
+    int k = 0;
+    bool nonfinite = false;
+    for (; k < n_outer;) {
+        const long long m = 1 + (long long)(growth / n_inner) * (first_round + k);
+        for (long long i = 0; i < m; ++i) {
+            HIP_TRY(c, hipGraphLaunch(steps[c->cur], c->stream));
+            if (n_inner & 1) c->cur = 1 - c->cur;
+        }
+        HIP_TRY(c, hipGraphLaunch(cons[c->cur], c->stream));
         ++k;
         if (tol > 0.0) {
             HIP_TRY(c, hipMemcpyAsync(c->h_pinned, c->res_last, sizeof(double), hipMemcpyDeviceToHost, c->stream));

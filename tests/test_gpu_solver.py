@@ -165,3 +165,28 @@ def test_tiny_problem_reaches_minimiser():
     xstar, kkt = minimiser.minimise(prob, tol=1e-12)
     assert rel_l2(xh, xstar) <= 1e-4, rel_l2(xh, xstar)
     ctx.close()
+
+
+def test_growing_schedule_matches_oracle():
+    """The paper's growing inexact schedule (round k runs n + g k steps): the
+    GPU run against the oracle with the same schedule, and one schedule split
+    over two calls equals it in one call."""
+    from paper_1705_06603_amd import _lib as dl
+    from tests._gpu import context_of, rel_l2
+    prob = _mid_problem(seed=4)
+    ctx = context_of(prob)
+    ctx.init()
+    res = ctx.run(3, 2, growth=2)
+    xh = ctx.assemble().cpu().numpy()
+    ref = solver.solve(prob, 3, 2, inner_growth=2)      # rounds of 2, 4 and 6 steps
+    assert rel_l2(xh, ref.x_hat) <= 1e-4
+    assert np.allclose(res, ref.residuals, rtol=1e-3, atol=0)
+    ctx.init()
+    res_a = ctx.run(2, 2, growth=2)
+    res_b = ctx.run(1, 2, growth=2, first_round=2)
+    assert res_a + res_b == res
+    assert np.array_equal(ctx.assemble().cpu().numpy(), xh)
+    with pytest.raises(dl.DeblurError) as e:
+        ctx.run(1, 4, growth=2)                          # growth not a multiple of n_inner
+    assert e.value.code == -1
+    ctx.close()
