@@ -201,6 +201,15 @@ int dev_alloc(deblur_ctx* c, T** ptr, size_t count) {
     return DEBLUR_OK;
 }
 
+// A device buffer used only during setup, freed on every return path.
+template <class T>
+struct ScratchBuf {
+    T* p = nullptr;
+    ~ScratchBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
 size_t frame_elems(const deblur_ctx* c) { return (size_t)c->nt * c->N * c->N; }
 size_t half_elems(const deblur_ctx* c) { return (size_t)c->nt * (c->N / 2) * c->N; }
 
@@ -642,11 +651,13 @@ int upload_tables(deblur_ctx* c, const float* psfs_host) {
     HIP_TRY(c, hipMemcpy(c->pd_block, pdb.data(), pdb.size() * sizeof(PackDesc), hipMemcpyHostToDevice));
 
     // PSF spectra
-    float* psf_d = nullptr;
-    double2* twd_d = nullptr;
+    ScratchBuf<float> psf_buf;
+    ScratchBuf<double2> twd_buf;
     const size_t npsf = (size_t)c->nodes * p.P * p.P;
-    HIP_TRY(c, hipMalloc(&psf_d, npsf * sizeof(float)));
-    HIP_TRY(c, hipMalloc(&twd_d, N * sizeof(double2)));
+    HIP_TRY(c, hipMalloc(&psf_buf.p, npsf * sizeof(float)));
+    HIP_TRY(c, hipMalloc(&twd_buf.p, N * sizeof(double2)));
+    float* psf_d = psf_buf.p;
+    double2* twd_d = twd_buf.p;
     if ((rc = dev_alloc(c, &c->spec, (size_t)c->nodes * (N / 2 + 1) * N))) return rc;
     HIP_TRY(c, hipMemcpy(psf_d, psfs_host, npsf * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(twd_d, twd.data(), N * sizeof(double2), hipMemcpyHostToDevice));
@@ -654,8 +665,6 @@ int upload_tables(deblur_ctx* c, const float* psfs_host) {
                        dim3(256), N * sizeof(double2), c->stream, psf_d, p.P, N, twd_d, c->spec);
     if ((rc = check_launch(c, "k_psf_spectra"))) return rc;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    HIP_TRY(c, hipFree(psf_d));
-    HIP_TRY(c, hipFree(twd_d));
     return DEBLUR_OK;
 }
 
@@ -712,8 +721,9 @@ int compute_rowsums(deblur_ctx* c) {
     hipLaunchKernelGGL(dbl::k_fill, dim3(1024), dim3(256), 0, c->stream, c->frame_tmp2, 1.0f, frame_elems(c));
     // ones on the supports only
     std::vector<float> ones((size_t)c->support_total, 1.0f);
-    float* ones_d = nullptr;
-    HIP_TRY(c, hipMalloc(&ones_d, std::max<size_t>(ones.size(), 1) * sizeof(float)));
+    ScratchBuf<float> ones_buf;
+    HIP_TRY(c, hipMalloc(&ones_buf.p, std::max<size_t>(ones.size(), 1) * sizeof(float)));
+    float* ones_d = ones_buf.p;
     HIP_TRY(c, hipMemcpy(ones_d, ones.data(), ones.size() * sizeof(float), hipMemcpyHostToDevice));
     hipLaunchKernelGGL(dbl::k_pack, frame_grid(c), dim3(256), 0, c->stream, ones_d, c->pd_support, c->N,
                        c->frame_tmp2);
@@ -723,7 +733,6 @@ int compute_rowsums(deblur_ctx* c) {
     int rc = check_launch(c, "row sums");
     if (rc) return rc;
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    HIP_TRY(c, hipFree(ones_d));
     return DEBLUR_OK;
 }
 
