@@ -350,8 +350,38 @@ void row_resid(deblur_ctx* c, hipStream_t s) { row_resid(c, s, all_tiles(c)); }
 void col_Ht(deblur_ctx* c, hipStream_t s) { col_Ht(c, s, all_tiles(c)); }
 void row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn) { row_update(c, s, xc, xn, all_tiles(c)); }
 
+// Resolves the frame kernels of a plan's shapes (loading their code) outside
+// any stream capture, so that a graph capture never makes a first use.
+template <int N, int WV>
+hipError_t preload_row(deblur_ctx*) {
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&dbl::k_row_resid<N, WV>));
+    if (e == hipSuccess) e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&dbl::k_row_update<N, WV>));
+    if (e == hipSuccess) e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&dbl::k_row_fwd<N, WV>));
+    if (e == hipSuccess) e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&dbl::k_row_inv<N, WV>));
+    return e;
+}
+template <int N, int WV>
+hipError_t preload_col(deblur_ctx*) {
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&dbl::k_col_H<N, WV>));
+    if (e == hipSuccess) e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&dbl::k_col_Ht<N, WV>));
+    return e;
+}
+
 int waves_hi(int N) { return N == 160 ? dbl::waves_hi<160>() : dbl::waves_hi<320>(); }
 int waves_lo(int N) { return waves_hi(N) / 2; }
+
+template <int N, int WV>
+void preload_row_v(deblur_ctx* c, hipError_t* e) { *e = preload_row<N, WV>(c); }
+template <int N, int WV>
+void preload_col_v(deblur_ctx* c, hipError_t* e) { *e = preload_col<N, WV>(c); }
+hipError_t preload_plan(deblur_ctx* c) {
+    hipError_t e1 = hipSuccess, e2 = hipSuccess;
+    DISPATCH_NW(c, c->plan.row_waves, preload_row_v, &e1);
+    DISPATCH_NW(c, c->plan.col_waves, preload_col_v, &e2);
+    return e1 != hipSuccess ? e1 : e2;
+}
 
 // Row workgroups per tile under the current plan, and the most any plan uses.
 int row_groups(const deblur_ctx* c) { return c->N / (c->plan.row_waves * (dbl::kPts / (c->N / 2))); }
@@ -828,6 +858,7 @@ int deblur_create(const deblur_params* params, const float* psfs_host, void* str
         return fail(nullptr, DEBLUR_E_HIP, "hipStreamCreate / hipEventCreate failed");
     }
     rc = upload_tables(c, psfs_host);
+    if (!rc && preload_plan(c) != hipSuccess) rc = fail(c, DEBLUR_E_HIP, "kernel code could not be loaded");
     if (!rc) rc = alloc_state(c);
     if (!rc) rc = compute_rowsums(c);
     if (rc) {
@@ -1198,6 +1229,7 @@ int deblur_set_plan(deblur_ctx* c, const deblur_plan* pl) {
     drop_graphs(c);
     c->plan = *pl;
     c->plan.frame = c->N;
+    HIP_TRY(c, preload_plan(c));
     return DEBLUR_OK;
 }
 
