@@ -163,11 +163,53 @@ template <int n> constexpr int nat_radix() {
     return first_radix<n, kFwd>();
 }
 
+// Padding of the LDS exchange after pass p of a length-n transform: element
+// f of the exchange is stored at f + (f / B) P.  LDS serves 16 lanes of a
+// 64-bit access per cycle from 32 four-byte banks, so an access is free of
+// bank conflicts when its 16 lanes' element positions are distinct mod 16.
+// Without padding, the stores of the first pass (stride R) and of the
+// inverse plan's middle pass fall on 4 positions mod 16.  B is a multiple of
+// the pass's butterfly span Ns R and of the lanes per line, and divides the
+// next pass's stride n / R', so the pad is one per-lane value for all of a
+// butterfly's stores and a compile-time offset for every load.  Lengths whose
+// lines are shorter than 16 lanes keep the unpadded layout (several lines
+// share one access there, and the line stride below separates them).
+template <int n, int DIR, int p> struct XPad { static constexpr int B = n, P = 0; };
+template <> struct XPad<320, kFwd, 0> { static constexpr int B = 80, P = 1; };
+template <> struct XPad<320, kFwd, 1> { static constexpr int B = 80, P = 4; };
+template <> struct XPad<320, kInv, 0> { static constexpr int B = 16, P = 1; };
+template <> struct XPad<640, kFwd, 0> { static constexpr int B = 160, P = 1; };
+template <> struct XPad<640, kFwd, 1> { static constexpr int B = 160, P = 4; };
+
+// A swizzle instead of a pad, for a pass whose butterflies span exactly one
+// aligned block of 16 elements (Ns R = 16) in 16-lane lines: element
+// 16 a + c is stored at 16 a + (c ^ Ns (a mod R)).  A butterfly's R stores
+// then land on R distinct positions mod 16 across the lanes that share an
+// access, and each load of the next pass is a lane index XORed with a
+// compile-time constant.  It needs no extra space.
+template <int n, int DIR, int p> struct XSwz { static constexpr bool on = false; };
+template <> struct XSwz<320, kInv, 1> { static constexpr bool on = true; };
+template <int n, int DIR, int p> constexpr int xpad_span() {
+    return n + ((n - 1) / XPad<n, DIR, p>::B) * XPad<n, DIR, p>::P;
+}
+template <int n, int DIR, int p = 0> constexpr int xpad_span_max() {
+    if constexpr (p + 1 >= Plan<n>::np) return n;
+    else return xpad_span<n, DIR, p>() > xpad_span_max<n, DIR, p + 1>() ? xpad_span<n, DIR, p>()
+                                                                         : xpad_span_max<n, DIR, p + 1>();
+}
+
 // Line stride (in float2) of the LDS exchange buffers.  It is odd, so the
 // column-wise (transposed) accesses of 16 consecutive lines hit distinct
-// banks.  When fewer than 16 lanes own a line, several lines share one
-// 16-lane LDS access; a stride = 9 (mod 32) puts those lines on disjoint banks.
-template <int n> constexpr int line_stride() { return (n / kV < 16) ? n + 9 : n + 1; }
+// banks, and it holds the padded exchanges.  When fewer than 16 lanes own a
+// line, several lines share one 16-lane LDS access; a stride = 9 (mod 32)
+// puts those lines on disjoint banks.
+template <int n> constexpr int line_stride() {
+    if constexpr (n / kV < 16) return n + 9;
+    else {
+        constexpr int f = xpad_span_max<n, kFwd>(), i = xpad_span_max<n, kInv>();
+        return (f > i ? f : i) | 1;
+    }
+}
 constexpr int kLinePad = 0;
 template <int n>
 __device__ __forceinline__ int line_off(int q) {
@@ -258,11 +300,24 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[kV], float2* __restrict__
         constexpr int LPL = lanes_per_line<n>();
         const int l = lane % LPL;
         float2* __restrict__ line = sw + line_off<n>(lane / LPL);
-        if constexpr (p > 0) {
+        if constexpr (p > 0 && XSwz<n, DIR, p - 1>::on) {
+            constexpr int SR = pass_radix<n, DIR, p - 1>(), SN = pass_ns<n, DIR, p - 1>();
+            static_assert(LPL == 16 && nR % 16 == 0, "exchange swizzle does not fit the loads");
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[b * R + r] = line[l + LPL * b + r * nR];
+                for (int r = 0; r < R; ++r) {
+                    const int a = (LPL * b + r * nR) / 16;   // block of this load (compile-time)
+                    v[b * R + r] = line[16 * a + (l ^ (SN * (a % SR)))];
+                }
+        } else if constexpr (p > 0) {
+            constexpr int PB = XPad<n, DIR, p - 1>::B, PP = XPad<n, DIR, p - 1>::P;
+            static_assert(PP == 0 || (PB % LPL == 0 && nR % PB == 0), "exchange padding does not fit the loads");
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    v[b * R + r] = line[l + LPL * b + r * nR + ((LPL * b) / PB + r * (nR / PB)) * PP];
         }
         // j = l + LPL b;  k = j mod Ns;  jd = j / Ns
         const int lm = l % Ns, ld = l / Ns;
@@ -280,7 +335,21 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[kV], float2* __restrict__
             dft<R, DIR>(&v[b * R]);
         }
         if constexpr (p + 1 < np) {
+            constexpr int XB = XPad<n, DIR, p>::B, XP = XPad<n, DIR, p>::P;
+            static_assert(XP == 0 || XB % (Ns * R) == 0, "exchange padding splits a butterfly");
             wave_sync();
+            if constexpr (XSwz<n, DIR, p>::on) {
+                static_assert(Ns * R == 16 && LPL % 16 == 0 && (LPL / Ns) % R == 0 && (R & (R - 1)) == 0,
+                              "exchange swizzle does not fit the stores");
+                // block a = jd = ld + b LPL / Ns, with jd mod R = ld mod R for every b
+                const int q = ld % R;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    float2* __restrict__ o = line + (ld + b * (LPL / Ns)) * 16 + lm;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) o[Ns * (r ^ q)] = v[b * R + r];
+                }
+            } else
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const int cb = LPL * b;
@@ -289,7 +358,8 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[kV], float2* __restrict__
                     k -= Ns;
                     jd += 1;
                 }
-                float2* __restrict__ o = line + jd * (Ns * R) + k;
+                const int f = jd * (Ns * R) + k;
+                float2* __restrict__ o = line + f + (f / XB) * XP;
 #pragma unroll
                 for (int r = 0; r < R; ++r) o[r * Ns] = v[b * R + r];
             }
