@@ -180,15 +180,20 @@ template <> struct XPad<320, kFwd, 1> { static constexpr int B = 80, P = 4; };
 template <> struct XPad<320, kInv, 0> { static constexpr int B = 16, P = 1; };
 template <> struct XPad<640, kFwd, 0> { static constexpr int B = 160, P = 1; };
 template <> struct XPad<640, kFwd, 1> { static constexpr int B = 160, P = 4; };
+template <> struct XPad<160, kFwd, 0> { static constexpr int B = 40, P = 1; };
+template <> struct XPad<160, kFwd, 1> { static constexpr int B = 80, P = 4; };
 
-// A swizzle instead of a pad, for a pass whose butterflies span exactly one
-// aligned block of 16 elements (Ns R = 16) in 16-lane lines: element
-// 16 a + c is stored at 16 a + (c ^ Ns (a mod R)).  A butterfly's R stores
-// then land on R distinct positions mod 16 across the lanes that share an
-// access, and each load of the next pass is a lane index XORed with a
-// compile-time constant.  It needs no extra space.
+// A swizzle instead of a pad, for a pass with power-of-two Ns and R whose
+// butterflies lie inside aligned blocks of Z = (lanes per line) elements:
+// element Z a + c is stored at Z a + (c ^ Ns (a mod R)), which permutes only
+// the R outputs of each butterfly.  Those then land on distinct positions
+// across the lanes that share an access, and each load of the next pass is
+// the lane index XORed with a compile-time constant.  It needs no extra
+// space.
 template <int n, int DIR, int p> struct XSwz { static constexpr bool on = false; };
 template <> struct XSwz<320, kInv, 1> { static constexpr bool on = true; };
+template <> struct XSwz<160, kInv, 0> { static constexpr bool on = true; };
+template <> struct XSwz<160, kInv, 1> { static constexpr bool on = true; };
 template <int n, int DIR, int p> constexpr int xpad_span() {
     return n + ((n - 1) / XPad<n, DIR, p>::B) * XPad<n, DIR, p>::P;
 }
@@ -214,6 +219,28 @@ constexpr int kLinePad = 0;
 template <int n>
 __device__ __forceinline__ int line_off(int q) {
     return q * line_stride<n>();
+}
+
+// With 8-lane lines two lines share each 16-lane access.  Their exchanges use
+// line bases shifted so that odd lines start 8 positions (mod 16) after the
+// even line before them: two lines whose 8 positions are distinct mod 8 then
+// fill all 16 positions.  The shift (by at most 8, into the unused tail of
+// the neighbouring line) keeps every exchange inside the wave's own lines.
+template <int n> constexpr int xline_shift() {
+    if constexpr (n / kV != 8) return 0;
+    else {
+        constexpr int s = ((8 - line_stride<n>()) % 16 + 16) % 16;
+        return s > 8 ? s - 16 : s;
+    }
+}
+template <int n>
+__device__ __forceinline__ int xline_off(int q) {
+    constexpr int sh = xline_shift<n>(), LS = line_stride<n>();
+    constexpr int span = xpad_span_max<n, kFwd>() > xpad_span_max<n, kInv>() ? xpad_span_max<n, kFwd>()
+                                                                             : xpad_span_max<n, kInv>();
+    static_assert(span <= LS + (sh < 0 ? sh : 0) && LS + (sh > 0 ? sh : 0) + span <= 2 * LS,
+                  "shifted exchange lines overlap");
+    return q * LS + (q & 1) * sh;
 }
 
 // Lanes per line: n = 20 * LPL.
@@ -299,16 +326,16 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[kV], float2* __restrict__
         constexpr int nR = n / R;
         constexpr int LPL = lanes_per_line<n>();
         const int l = lane % LPL;
-        float2* __restrict__ line = sw + line_off<n>(lane / LPL);
+        float2* __restrict__ line = sw + xline_off<n>(lane / LPL);
         if constexpr (p > 0 && XSwz<n, DIR, p - 1>::on) {
             constexpr int SR = pass_radix<n, DIR, p - 1>(), SN = pass_ns<n, DIR, p - 1>();
-            static_assert(LPL == 16 && nR % 16 == 0, "exchange swizzle does not fit the loads");
+            static_assert(nR % LPL == 0, "exchange swizzle does not fit the loads");
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const int a = (LPL * b + r * nR) / 16;   // block of this load (compile-time)
-                    v[b * R + r] = line[16 * a + (l ^ (SN * (a % SR)))];
+                    const int a = b + r * (nR / LPL);   // block of this load (compile-time)
+                    v[b * R + r] = line[LPL * a + (l ^ (SN * (a % SR)))];
                 }
         } else if constexpr (p > 0) {
             constexpr int PB = XPad<n, DIR, p - 1>::B, PP = XPad<n, DIR, p - 1>::P;
@@ -339,13 +366,14 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[kV], float2* __restrict__
             static_assert(XP == 0 || XB % (Ns * R) == 0, "exchange padding splits a butterfly");
             wave_sync();
             if constexpr (XSwz<n, DIR, p>::on) {
-                static_assert(Ns * R == 16 && LPL % 16 == 0 && (LPL / Ns) % R == 0 && (R & (R - 1)) == 0,
+                static_assert(LPL % (Ns * R) == 0 && LPL % Ns == 0 && (R & (R - 1)) == 0 && (Ns & (Ns - 1)) == 0,
                               "exchange swizzle does not fit the stores");
-                // block a = jd = ld + b LPL / Ns, with jd mod R = ld mod R for every b
-                const int q = ld % R;
+                // butterfly jd = ld + b LPL / Ns starts at element jd Ns R + lm, in block
+                // a = jd / (LPL / (Ns R)); a mod R is the same for every b
+                const int q = (ld / (LPL / (Ns * R))) % R;
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
-                    float2* __restrict__ o = line + (ld + b * (LPL / Ns)) * 16 + lm;
+                    float2* __restrict__ o = line + ld * (Ns * R) + lm + b * (LPL * R);
 #pragma unroll
                     for (int r = 0; r < R; ++r) o[Ns * (r ^ q)] = v[b * R + r];
                 }
