@@ -659,6 +659,16 @@ __device__ __forceinline__ float reg_scale(float gh, float gv, const SolveParams
     return P.reg_param * __frcp_rn(fmaxf(sqrtf(n2), P.reg_param));
 }
 
+// Value of v in the next (lane + 1) and previous (lane - 1) lane of the wave,
+// by a whole-wave DPP shift (a VALU operation, no LDS traffic); lane 63
+// resp. lane 0 receive 0.  Every lane must execute the call.
+__device__ __forceinline__ float from_next_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_prev_lane(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+
 // Tasks of the column-strip update phase: every column split into segments
 // of kSeg rows, (N / RB-row workgroup) -> N * RB / kSeg tasks, a multiple of NT.
 constexpr int kSeg = 8;
@@ -770,7 +780,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                 // vertical flux of the row above the strip
                 float qv_up = 0.f;
                 {
-                    const float xr = __shfl_down(X[0], 1);
+                    const float xr = from_next_lane(X[0]);
                     if (colin && ia >= 1 && ia < sy) {
                         const float gh = rin ? xr - X[0] : 0.f;
                         const float gv = X[1] - X[0];
@@ -783,12 +793,12 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                     const int i = ia + k;
                     const bool pin = colin && i < sy;
                     const float xm = X[k + 1];
-                    const float xr = __shfl_down(xm, 1);
+                    const float xr = from_next_lane(xm);
                     const float gh = (pin && rin) ? xr - xm : 0.f;
                     const float gv = (pin && i + 1 < sy) ? X[k + 2] - xm : 0.f;
                     const float sc = reg_scale(gh, gv, P);
                     const float qh = sc * gh, qv = sc * gv;
-                    const float qh_l = __shfl_up(qh, 1);
+                    const float qh_l = from_prev_lane(qh);
                     float val = 0.f;
                     if (pin) {
                         // -div of the flux (s gh, s gv): backward differences
