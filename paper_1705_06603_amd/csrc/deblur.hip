@@ -813,12 +813,14 @@ const char* deblur_last_error(const deblur_ctx* ctx) {
 
 void deblur_destroy(deblur_ctx* c) {
     if (!c) return;
+    // every stream that may still run this context's kernels drains before
+    // any of its memory is released
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (hipStream_t a : c->aux_stream)
+        if (a) (void)hipStreamSynchronize(a);
     drop_graphs(c);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
-    for (hipStream_t a : c->aux_stream)
-        if (a) (void)hipStreamSynchronize(a);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (int g = 0; g < kMaxGroups - 1; ++g) {
         if (c->cap_aux[g]) (void)hipStreamDestroy(c->cap_aux[g]);
