@@ -296,10 +296,17 @@ def convergence(ctx, w, args):
     B = ctx.n_tiles
     ms_all, ms_mid = net.time_forward(frames, reps=10)
     flop_mid = 2.0 * 9 * 32 * 32 * B * N * N
+    # the 32 -> 32 layer reads and writes one bf16 activation map of 32
+    # channels: 144 flop per byte, below the bf16 MFMA / HBM balance of
+    # 2500 / 8 = 312, so its roofline is the HBM one
+    bytes_mid = 2.0 * 32 * 2 * B * N * N
     out["network"] = {"forward_ms_per_batch": round(ms_all, 3), "batch_tiles": B, "frame": N,
                       "mid_layer_ms": round(ms_mid, 4), "mid_layer_TFLOPs": round(flop_mid / (ms_mid * 1e-3) / 1e12, 1),
                       "mfma_bf16_peak_TFLOPs": 2500.0,
-                      "mfma_utilisation": round(flop_mid / (ms_mid * 1e-3) / 2.5e15, 4)}
+                      "mfma_utilisation": round(flop_mid / (ms_mid * 1e-3) / 2.5e15, 4),
+                      "mid_layer_algorithmic_bytes": bytes_mid,
+                      "mid_layer_GBps": round(bytes_mid / (ms_mid * 1e-3) / 1e9, 1),
+                      "mid_layer_hbm_frac": round(bytes_mid / (ms_mid * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     net.close()
     return out
 
