@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import itertools
 import json
 import os
 import sys
@@ -166,7 +167,7 @@ def _oracle_tile_steps(job):
     x0 = solver.initial_tiles(prob, "observed")
     el, steps = 0.0, 0
     t_start = time.perf_counter()
-    for t in tiles:
+    for t in itertools.cycle(tiles):   # the worker's tiles, again until the budget is spent
         tau = solver.step_size(prob, t)          # setup, not timed
         ts = time.perf_counter()
         solver.local_solve(prob, t, x0[t], x0[t], 1, tau)
@@ -210,7 +211,7 @@ def cpu_baseline(pool, procs, psfs, y, W, w, budget_s=20.0):
     rate = (w.M * w.M) * tile_steps_per_s / L.n_tiles / 1e6
     return {"value": rate, "unit": UNIT, "cores": procs, "kind": "oracle",
             "sample": f"1 Local-Solver step (H + H^T + TV gradient + projected update) of the fp64 "
-                      f"direct-convolution oracle on {steps} seeded-random tiles of {L.n_tiles}, in {procs} "
+                      f"direct-convolution oracle, {steps} tile-steps over {L.n_tiles} seeded-shuffled tiles, in {procs} "
                       f"single-threaded processes for ~{budget_s:.0f} s each; whole-image rate = sum of the "
                       f"processes' tile-step rates x (image pixels / tiles)"}
 
