@@ -169,9 +169,10 @@ template <int n> constexpr int nat_radix() {
 // bank conflicts when its 16 lanes' element positions are distinct mod 16.
 // Without padding, the stores of the first pass (stride R) and of the
 // inverse plan's middle pass fall on 4 positions mod 16.  B is a multiple of
-// the pass's butterfly span Ns R and of the lanes per line, and divides the
-// next pass's stride n / R', so the pad is one per-lane value for all of a
-// butterfly's stores and a compile-time offset for every load.  Lengths whose
+// the pass's butterfly span Ns R, divides the next pass's stride n / R', and
+// is a multiple or a divisor of the lanes per line, so the pad is one
+// per-lane value for all of a butterfly's stores and a per-lane value plus a
+// compile-time offset for every load.  Lengths whose
 // lines are shorter than 16 lanes keep the unpadded layout (several lines
 // share one access there, and the line stride below separates them).
 template <int n, int DIR, int p> struct XPad { static constexpr int B = n, P = 0; };
@@ -180,6 +181,7 @@ template <> struct XPad<320, kFwd, 1> { static constexpr int B = 80, P = 4; };
 template <> struct XPad<320, kInv, 0> { static constexpr int B = 16, P = 1; };
 template <> struct XPad<640, kFwd, 0> { static constexpr int B = 160, P = 1; };
 template <> struct XPad<640, kFwd, 1> { static constexpr int B = 160, P = 4; };
+template <> struct XPad<640, kInv, 0> { static constexpr int B = 16, P = 1; };
 template <> struct XPad<160, kFwd, 0> { static constexpr int B = 40, P = 1; };
 template <> struct XPad<160, kFwd, 1> { static constexpr int B = 80, P = 4; };
 
@@ -194,6 +196,7 @@ template <int n, int DIR, int p> struct XSwz { static constexpr bool on = false;
 template <> struct XSwz<320, kInv, 1> { static constexpr bool on = true; };
 template <> struct XSwz<160, kInv, 0> { static constexpr bool on = true; };
 template <> struct XSwz<160, kInv, 1> { static constexpr bool on = true; };
+template <> struct XSwz<640, kInv, 2> { static constexpr bool on = true; };
 template <int n, int DIR, int p> constexpr int xpad_span() {
     return n + ((n - 1) / XPad<n, DIR, p>::B) * XPad<n, DIR, p>::P;
 }
@@ -339,12 +342,15 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[kV], float2* __restrict__
                 }
         } else if constexpr (p > 0) {
             constexpr int PB = XPad<n, DIR, p - 1>::B, PP = XPad<n, DIR, p - 1>::P;
-            static_assert(PP == 0 || (PB % LPL == 0 && nR % PB == 0), "exchange padding does not fit the loads");
+            static_assert(PP == 0 || ((PB % LPL == 0 || LPL % PB == 0) && nR % PB == 0),
+                          "exchange padding does not fit the loads");
+            // (l + LPL b + r nR) / PB = l / PB + (LPL b) / PB + r nR / PB
+            const int lp = (PP != 0 && PB < LPL) ? (l / PB) * PP : 0;
 #pragma unroll
             for (int b = 0; b < NB; ++b)
 #pragma unroll
                 for (int r = 0; r < R; ++r)
-                    v[b * R + r] = line[l + LPL * b + r * nR + ((LPL * b) / PB + r * (nR / PB)) * PP];
+                    v[b * R + r] = line[lp + l + LPL * b + r * nR + ((LPL * b) / PB + r * (nR / PB)) * PP];
         }
         // j = l + LPL b;  k = j mod Ns;  jd = j / Ns
         const int lm = l % Ns, ld = l / Ns;
@@ -376,6 +382,17 @@ __device__ __forceinline__ void fft_passes(float2 (&v)[kV], float2* __restrict__
                     float2* __restrict__ o = line + ld * (Ns * R) + lm + b * (LPL * R);
 #pragma unroll
                     for (int r = 0; r < R; ++r) o[Ns * (r ^ q)] = v[b * R + r];
+                }
+            } else if constexpr (XP != 0 && LPL % Ns == 0 && (LPL * R) % XB == 0) {
+                // butterfly jd = ld + b LPL / Ns starts at element ld Ns R + lm + b LPL R,
+                // and its pad is the b = 0 pad plus b (LPL R / XB) P
+                const int f0 = ld * (Ns * R) + lm;
+                float2* __restrict__ o0 = line + f0 + (f0 / XB) * XP;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    float2* __restrict__ o = o0 + b * (LPL * R + (LPL * R / XB) * XP);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) o[r * Ns] = v[b * R + r];
                 }
             } else
 #pragma unroll
