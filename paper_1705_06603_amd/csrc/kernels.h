@@ -755,8 +755,8 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
             // column, lanes 0 and 63 are halo.  Each lane evaluates the
             // regulariser scale of its own pixel once; x(i, c + 1) and the
             // left neighbour's horizontal flux s gh come from the adjacent
-            // lanes.  The loads of a wave's next task are issued before the
-            // current task is computed (two register buffers).
+            // lanes.  The loads of a wave's next two tasks are in flight while
+            // the current task is computed (three register buffers).
             constexpr int OWN = kLanes - 2;
             constexpr int NCG = (N + OWN - 1) / OWN;
             constexpr int NTASK = NCG * SEGS;
@@ -812,15 +812,19 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                     if (lane >= 1 && lane <= OWN && c < N) xo[i * N + c] = val;
                 }
             };
-            float XA[kSeg + 2], UA[kSeg], XB[kSeg + 2], UB[kSeg];
+            float XA[kSeg + 2], UA[kSeg], XB[kSeg + 2], UB[kSeg], XC[kSeg + 2], UC[kSeg];
+            constexpr int S = C::W;   // task stride of a wave
             if (wave < NTASK) load(wave, XA, UA);
-            for (int task = wave; task < NTASK; task += 2 * C::W) {
-                const int tb = task + C::W;
-                if (tb < NTASK) load(tb, XB, UB);
+            if (wave + S < NTASK) load(wave + S, XB, UB);
+            for (int task = wave; task < NTASK; task += 3 * S) {
+                if (task + 2 * S < NTASK) load(task + 2 * S, XC, UC);
                 update(task, XA, UA);
-                if (tb >= NTASK) break;
-                if (tb + C::W < NTASK) load(tb + C::W, XA, UA);
-                update(tb, XB, UB);
+                if (task + S >= NTASK) break;
+                if (task + 3 * S < NTASK) load(task + 3 * S, XA, UA);
+                update(task + S, XB, UB);
+                if (task + 2 * S >= NTASK) break;
+                if (task + 4 * S < NTASK) load(task + 4 * S, XB, UB);
+                update(task + 2 * S, XC, UC);
             }
         } else
         // Circular differences: one thread per (column, kSeg rows), x at
