@@ -32,10 +32,17 @@ KERNELS_PER_STEP = ("col_H", "row_resid", "col_Ht", "row_update")
 
 
 def kernel_source_hash():
+    """Hash of the frame kernels' code (fft_core.h + kernels.h) with comments
+    and blank lines removed, so that recorded counters stay matched to the
+    code they were taken on across comment-only edits."""
+    import re
     h = hashlib.sha256()
     for f in ("fft_core.h", "kernels.h"):
-        with open(os.path.join(ROOT, "paper_1705_06603_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1705_06603_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = (re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines())
+        h.update("\n".join(ln for ln in lines if ln).encode())
     return h.hexdigest()[:16]
 
 

@@ -172,9 +172,10 @@ template <int n> constexpr int nat_radix() {
 // the pass's butterfly span Ns R, divides the next pass's stride n / R', and
 // is a multiple or a divisor of the lanes per line, so the pad is one
 // per-lane value for all of a butterfly's stores and a per-lane value plus a
-// compile-time offset for every load.  Lengths whose
-// lines are shorter than 16 lanes keep the unpadded layout (several lines
-// share one access there, and the line stride below separates them).
+// compile-time offset for every load.  With 8-lane lines, two lines share an
+// access; the odd-line shift below (xline_off) puts them on disjoint banks,
+// and the pads only need distinct positions mod 8 within a line.  The
+// 80-point rows (4-lane lines) keep the unpadded layout.
 template <int n, int DIR, int p> struct XPad { static constexpr int B = n, P = 0; };
 template <> struct XPad<320, kFwd, 0> { static constexpr int B = 80, P = 1; };
 template <> struct XPad<320, kFwd, 1> { static constexpr int B = 80, P = 4; };
