@@ -14,7 +14,8 @@ Modules:
               spatial convolution (Section II-B), the global operator used to
               simulate data (Eq. (2)), and an FP64 FFT backend
   prior    -- smoothed total variation and Huber regularisers (Section IV-A)
-  solver   -- Local-Solver (projected gradient on the prox subproblem),
+  solver   -- Local-Solver (projected gradient on the prox subproblem, or its
+              FISTA-accelerated form),
               consensus by the Lemma of Section III-B, the D-R outer loop of
               Algorithm 1, residual and output assembly
   minimiser-- the result oracle: a direct minimiser of the consensus problem

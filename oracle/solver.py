@@ -24,6 +24,18 @@ max(omega_t), an upper bound on the Lipschitz constant of the gradient
 (max(H_t 1) is the largest row sum of H_t; its column sums are at most 1 for
 non-negative unit-sum PSFs and tents summing to one, so ||H_t||^2 <= max(H_t 1)).
 
+A second Local-Solver (method "fista") takes the same gradient steps with
+Nesterov momentum, as in FISTA (Beck and Teboulle, 2009, the accelerated
+proximal-gradient method the paper cites among fast first-order solvers):
+
+    w_j = max(0, y_j - tau_t g(y_j)),
+    y_{j+1} = w_j + beta_j (w_j - w_{j-1}),  beta_j = (s_j - 1) / s_{j+1},
+    s_1 = 1,  s_{j+1} = (1 + sqrt(1 + 4 s_j^2)) / 2,
+
+restarted at every call from y_1 = w_0 = the warm start.  The run returns
+w_n, so the last step's momentum (which would only move the unused y_{n+1})
+is taken as 0.
+
 One "iteration" is one projected-gradient step on every tile; consensus runs
 after every n_inner of them.  The residual is the D-R fixed-point residual
 ||u^{k+1} - u^k|| / ||u^{k+1}|| over all tiles.  The output image is
@@ -109,14 +121,41 @@ def prox_gradient(problem, t, w, u):
     return g + problem.alpha_t(t) * (w - u)
 
 
-def local_solve(problem, t, w0, u, n_inner, tau=None):
-    """n_inner projected-gradient steps on the prox subproblem of tile t."""
+def fista_momentum(n_inner):
+    """Momentum factors beta_1 .. beta_n of an n-step FISTA run (the module
+    docstring): s_1 = 1, s_{j+1} = (1 + sqrt(1 + 4 s_j^2)) / 2, beta_j =
+    (s_j - 1) / s_{j+1}, with beta_n = 0 (the run ends on w_n)."""
+    beta = []
+    s = 1.0
+    for j in range(n_inner):
+        s_next = (1.0 + np.sqrt(1.0 + 4.0 * s * s)) / 2.0
+        beta.append((s - 1.0) / s_next if j + 1 < n_inner else 0.0)
+        s = s_next
+    return beta
+
+
+def local_solve(problem, t, w0, u, n_inner, tau=None, method="pg"):
+    """n_inner steps on the prox subproblem of tile t: projected gradient
+    ("pg") or its accelerated form ("fista", see the module docstring)."""
     tau = step_size(problem, t) if tau is None else tau
+    if method == "pg":
+        w = w0.copy()
+        for _ in range(n_inner):
+            w = w - tau * prox_gradient(problem, t, w, u)
+            if problem.positivity:
+                w = np.maximum(w, 0.0)
+        return w
+    if method != "fista":
+        raise ValueError(method)
+    w_prev = w0.copy()
+    y = w0.copy()
     w = w0.copy()
-    for _ in range(n_inner):
-        w = w - tau * prox_gradient(problem, t, w, u)
+    for beta in fista_momentum(n_inner):
+        w = y - tau * prox_gradient(problem, t, y, u)
         if problem.positivity:
             w = np.maximum(w, 0.0)
+        y = w + beta * (w - w_prev)
+        w_prev = w
     return w
 
 
@@ -196,12 +235,13 @@ class Result:
 
 
 def solve(problem, n_outer, n_inner=10, init="observed", x0=None, inner_growth=0,
-          consensus=True, callback=None):
+          consensus=True, callback=None, local_solver="pg"):
     """Algorithm 1 with n_inner(k) = n_inner + inner_growth * k Local-Solver steps.
 
     ``consensus=False`` skips the consensus step (the paper's 'independent'
     baseline: each tile is deblurred on its own and the tiles are blended
-    with omega at the end).
+    with omega at the end).  ``local_solver`` is "pg" or "fista"; a FISTA
+    run restarts in every round.
     """
     x = [a.copy() for a in (x0 if x0 is not None else initial_tiles(problem, init))]
     u = [a.copy() for a in x]
@@ -209,7 +249,7 @@ def solve(problem, n_outer, n_inner=10, init="observed", x0=None, inner_growth=0
     res = []
     for k in range(n_outer):
         n_k = n_inner + inner_growth * k
-        x = [local_solve(problem, t, x[t], u[t], n_k, taus[t]) for t in range(problem.n_tiles)]
+        x = [local_solve(problem, t, x[t], u[t], n_k, taus[t], local_solver) for t in range(problem.n_tiles)]
         if consensus:
             u_new, _ = consensus_step(problem, x, u)
         else:
