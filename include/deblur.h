@@ -73,6 +73,20 @@ enum {
     DEBLUR_BC_CIRCULAR = 1    /* difference wraps within the support           */
 };
 
+/* Local-Solver of Algorithm 1 (Section III-B; Section IV-B allows any fast
+ * first-order method).  Both take steps of length tau_t = 1/L_t on the prox
+ * objective f_t(w) + 1/2 ||w - u_t||^2_alpha with projection onto w >= 0.
+ * FISTA adds Nesterov momentum (Beck-Teboulle): w_j = P(y_j - tau g(y_j)),
+ * y_{j+1} = w_j + beta_j (w_j - w_{j-1}), beta_j = (s_j - 1)/s_{j+1}, s_1 = 1,
+ * s_{j+1} = (1 + sqrt(1 + 4 s_j^2))/2, restarted at every run of n steps
+ * (each D-R round, each deblur_solve_tiles call) from y_1 = the current x, and
+ * ending on w_n (the last step's beta is 0).  It keeps one more frame per tile
+ * and is not available with the growing schedule. */
+enum {
+    DEBLUR_SOLVER_PG = 0,     /* projected gradient                              */
+    DEBLUR_SOLVER_FISTA = 1   /* accelerated projected gradient (FISTA)          */
+};
+
 enum {
     DEBLUR_INIT_ZERO = 0,     /* x0 = 0                                          */
     DEBLUR_INIT_OBSERVED = 1, /* x0 = max(y, 0) at the nearest observed pixel     */
@@ -95,6 +109,7 @@ typedef struct deblur_params {
     float reg_param;      /* eps (smoothed TV) or delta (Huber), > 0      */
     float gamma;          /* metric alpha_t = gamma * omega_t, > 0        */
     float rho;            /* D-R relaxation, in (0, 2)                    */
+    int32_t local_solver; /* DEBLUR_SOLVER_*                              */
 } deblur_params;
 
 typedef struct deblur_tile_desc {

@@ -18,6 +18,7 @@ MODEL_INTERP, MODEL_LOCAL = 0, 1
 REG_SMOOTH_TV, REG_HUBER = 0, 1
 BC_NEUMANN, BC_CIRCULAR = 0, 1
 INIT_ZERO, INIT_OBSERVED, INIT_GIVEN = 0, 1, 2
+SOLVER_PG, SOLVER_FISTA = 0, 1
 N_KERNELS = 5
 KERNEL_NAMES = ("col_H", "row_resid", "col_Ht", "row_update", "consensus")
 
@@ -44,6 +45,7 @@ class Params(ctypes.Structure):
         ("positivity", ctypes.c_int32), ("fft_size", ctypes.c_int32),
         ("lambda_", ctypes.c_float), ("reg_param", ctypes.c_float),
         ("gamma", ctypes.c_float), ("rho", ctypes.c_float),
+        ("local_solver", ctypes.c_int32),
     ]
 
 
@@ -164,7 +166,7 @@ def _stream_handle(stream):
 
 def make_params(M, T, pitch, overlap, G, P, *, model=MODEL_INTERP, reg=REG_SMOOTH_TV, bc=BC_NEUMANN,
                 positivity=True, fft_size=0, lam=1e-3, reg_param=1e-3, gamma=0.4, rho=1.0,
-                M_x=None, T_x=None, G_x=None):
+                M_x=None, T_x=None, G_x=None, local_solver=SOLVER_PG):
     p = Params()
     p.M_y, p.M_x = M, M if M_x is None else M_x
     p.T_y, p.T_x = T, T if T_x is None else T_x
@@ -173,6 +175,7 @@ def make_params(M, T, pitch, overlap, G, P, *, model=MODEL_INTERP, reg=REG_SMOOT
     p.P, p.model, p.reg, p.bc = P, model, reg, bc
     p.positivity, p.fft_size = int(bool(positivity)), fft_size
     p.lambda_, p.reg_param, p.gamma, p.rho = lam, reg_param, gamma, rho
+    p.local_solver = local_solver
     return p
 
 

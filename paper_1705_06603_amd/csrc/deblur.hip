@@ -153,6 +153,8 @@ struct deblur_ctx {
     int* bdim = nullptr;
     double* gmap = nullptr;
     int* use_cnn = nullptr;
+    bool fista = false;           // Local-Solver: FISTA (else projected gradient)
+    float* wbuf = nullptr;        // FISTA: the last projected-gradient point w_j per tile frame
     std::vector<void*> allocs;
     std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;   // (steps, parity, with consensus)
     std::vector<hipGraph_t> graph_defs;
@@ -282,10 +284,27 @@ SolveParams solve_params(const deblur_ctx* c) {
     return P;
 }
 template <int N, int WV>
-void launch_row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn, TileRange r) {
+void launch_row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn, TileRange r, float beta) {
     using C = dbl::Cfg<N, WV>;
-    hipLaunchKernelGGL((dbl::k_row_update<N, WV>), dim3(C::RG, r.cnt), dim3(C::NT), 0, s, c->Gk, xc, c->u, c->tiles,
-                       c->tentX, c->omY, c->omX, c->tau, solve_params(c), c->tw, xn, c->Zk, r.t0);
+    if (c->fista)
+        hipLaunchKernelGGL((dbl::k_row_update<N, WV, true>), dim3(C::RG, r.cnt), dim3(C::NT), 0, s, c->Gk, xc, c->u,
+                           c->tiles, c->tentX, c->omY, c->omX, c->tau, solve_params(c), c->tw, xn, c->Zk, r.t0, beta,
+                           c->wbuf);
+    else
+        hipLaunchKernelGGL((dbl::k_row_update<N, WV, false>), dim3(C::RG, r.cnt), dim3(C::NT), 0, s, c->Gk, xc, c->u,
+                           c->tiles, c->tentX, c->omY, c->omX, c->tau, solve_params(c), c->tw, xn, c->Zk, r.t0, 0.f,
+                           nullptr);
+}
+
+// Momentum factor of step j (0-based) of an n-step FISTA run: with s_1 = 1,
+// s_{i+1} = (1 + sqrt(1 + 4 s_i^2)) / 2, step j uses (s_{j+1} - 1) / s_{j+2};
+// the last step uses 0, so the run ends on its projected-gradient point.
+float fista_beta(int j, int n) {
+    if (j + 1 >= n) return 0.f;
+    double s = 1.0;
+    for (int i = 0; i < j; ++i) s = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * s * s));
+    const double s_next = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * s * s));
+    return (float)((s - 1.0) / s_next);
 }
 
 template <int N, int WV>
@@ -342,13 +361,15 @@ void row_resid(deblur_ctx* c, hipStream_t s, TileRange r) {
     DISPATCH_NW(c, c->plan.row_waves, launch_row_resid, s, r);
 }
 void col_Ht(deblur_ctx* c, hipStream_t s, TileRange r) { DISPATCH_NW(c, c->plan.col_waves, launch_col_Ht, s, r); }
-void row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn, TileRange r) {
-    DISPATCH_NW(c, c->plan.row_waves, launch_row_update, s, xc, xn, r);
+void row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn, TileRange r, float beta = 0.f) {
+    DISPATCH_NW(c, c->plan.row_waves, launch_row_update, s, xc, xn, r, beta);
 }
 void col_H(deblur_ctx* c, hipStream_t s) { col_H(c, s, all_tiles(c)); }
 void row_resid(deblur_ctx* c, hipStream_t s) { row_resid(c, s, all_tiles(c)); }
 void col_Ht(deblur_ctx* c, hipStream_t s) { col_Ht(c, s, all_tiles(c)); }
-void row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn) { row_update(c, s, xc, xn, all_tiles(c)); }
+void row_update(deblur_ctx* c, hipStream_t s, const float* xc, float* xn, float beta = 0.f) {
+    row_update(c, s, xc, xn, all_tiles(c), beta);
+}
 
 // Resolves the frame kernels of a plan's shapes (loading their code) outside
 // any stream capture, so that a graph capture never makes a first use.
@@ -356,7 +377,8 @@ template <int N, int WV>
 hipError_t preload_row(deblur_ctx*) {
     hipFuncAttributes a;
     hipError_t e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&dbl::k_row_resid<N, WV>));
-    if (e == hipSuccess) e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&dbl::k_row_update<N, WV>));
+    if (e == hipSuccess) e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&dbl::k_row_update<N, WV, false>));
+    if (e == hipSuccess) e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&dbl::k_row_update<N, WV, true>));
     if (e == hipSuccess) e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&dbl::k_row_fwd<N, WV>));
     if (e == hipSuccess) e = hipFuncGetAttributes(&a, reinterpret_cast<const void*>(&dbl::k_row_inv<N, WV>));
     return e;
@@ -396,14 +418,18 @@ dim3 frame_grid(const deblur_ctx* c) {
     return dim3(std::min(per, 64), c->nt);
 }
 
-// One Local-Solver step on the tiles of r: x[cur] -> x[1 - cur].
-void inner_step(deblur_ctx* c, hipStream_t s, int parity, TileRange r) {
+// One Local-Solver step on the tiles of r: x[cur] -> x[1 - cur] (with FISTA,
+// from the gradient point y_j to y_{j+1}, with momentum beta).
+void inner_step(deblur_ctx* c, hipStream_t s, int parity, TileRange r, float beta = 0.f) {
     col_H(c, s, r);
     row_resid(c, s, r);
     col_Ht(c, s, r);
-    row_update(c, s, c->x[parity], c->x[1 - parity], r);
+    row_update(c, s, c->x[parity], c->x[1 - parity], r, beta);
 }
-void inner_step(deblur_ctx* c, hipStream_t s, int parity) { inner_step(c, s, parity, all_tiles(c)); }
+void inner_step(deblur_ctx* c, hipStream_t s, int parity, float beta = 0.f) {
+    inner_step(c, s, parity, all_tiles(c), beta);
+}
+float step_beta(const deblur_ctx* c, int i, int n) { return c->fista ? fista_beta(i, n) : 0.f; }
 
 // n Local-Solver steps on every tile starting from x[parity].  With G > 1
 // tile groups the groups run as G independent chains, on s and on aux[0 ..
@@ -413,7 +439,7 @@ hipError_t local_steps(deblur_ctx* c, hipStream_t s, hipStream_t* aux, int n, in
     if (n == 0) return hipSuccess;
     const int G = std::min(c->plan.tile_groups, c->nt);
     if (G <= 1) {
-        for (int i = 0; i < n; ++i, parity = 1 - parity) inner_step(c, s, parity);
+        for (int i = 0; i < n; ++i, parity = 1 - parity) inner_step(c, s, parity, step_beta(c, i, n));
         return hipGetLastError();
     }
     hipError_t e = hipEventRecord(c->ev_fork, s);
@@ -422,7 +448,7 @@ hipError_t local_steps(deblur_ctx* c, hipStream_t s, hipStream_t* aux, int n, in
     TileRange rg[kMaxGroups];
     for (int g = 0; g < G; ++g) rg[g] = tile_group(c, g);
     for (int i = 0, p = parity; i < n; ++i, p = 1 - p)
-        for (int g = 0; g < G; ++g) inner_step(c, g ? aux[g - 1] : s, p, rg[g]);
+        for (int g = 0; g < G; ++g) inner_step(c, g ? aux[g - 1] : s, p, rg[g], step_beta(c, i, n));
     for (int g = 1; g < G && e == hipSuccess; ++g) {
         e = hipEventRecord(c->ev_join[g - 1], aux[g - 1]);
         if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_join[g - 1], 0);
@@ -726,6 +752,10 @@ int alloc_state(deblur_ctx* c) {
     if ((rc = dev_alloc(c, &c->tile_scale, c->nt))) return rc;
     if ((rc = dev_alloc(c, &c->gmap, 2 * (size_t)c->nt))) return rc;
     if ((rc = dev_alloc(c, &c->use_cnn, c->nt))) return rc;
+    if (c->fista) {
+        if ((rc = dev_alloc(c, &c->wbuf, fe))) return rc;
+        HIP_TRY(c, hipMemsetAsync(c->wbuf, 0, fe * sizeof(float), c->stream));
+    }
     HIP_TRY(c, hipHostMalloc((void**)&c->h_pinned, 64 * sizeof(double), hipHostMallocDefault));
     // zero everything that is read before being written
     for (float* f : {c->x[0], c->x[1], c->u, c->frame_tmp, c->frame_tmp2})
@@ -841,8 +871,11 @@ int deblur_create(const deblur_params* params, const float* psfs_host, void* str
     if (p.bc != DEBLUR_BC_NEUMANN && p.bc != DEBLUR_BC_CIRCULAR) return fail(nullptr, DEBLUR_E_ARG, "bc");
     if (!(p.reg_param > 0.f) || !(p.gamma > 0.f) || !(p.lambda >= 0.f) || !(p.rho > 0.f && p.rho < 2.f))
         return fail(nullptr, DEBLUR_E_ARG, "need reg_param > 0, gamma > 0, lambda >= 0, 0 < rho < 2");
+    if (p.local_solver != DEBLUR_SOLVER_PG && p.local_solver != DEBLUR_SOLVER_FISTA)
+        return fail(nullptr, DEBLUR_E_ARG, "local_solver");
     deblur_ctx* c = new deblur_ctx();
     c->p = p;
+    c->fista = p.local_solver == DEBLUR_SOLVER_FISTA;
     c->stream = static_cast<hipStream_t>(stream);
     int rc = build_layout(c, psfs_host);
     if (rc) {
@@ -1029,6 +1062,8 @@ int deblur_run_schedule(deblur_ctx* c, int32_t n_outer, int32_t n_inner, int32_t
     if (!c || n_outer < 0 || n_inner < 1 || growth < 0 || first_round < 0)
         return fail(c, DEBLUR_E_ARG, "bad argument");
     if (growth % n_inner) return fail(c, DEBLUR_E_ARG, "growth must be a multiple of n_inner");
+    if (growth > 0 && c->fista)
+        return fail(c, DEBLUR_E_ARG, "the growing schedule runs projected-gradient steps only");
     if (growth == 0) return deblur_run(c, n_outer, n_inner, tol, residuals, done);
     if (n_outer > kResCap) return fail(c, DEBLUR_E_ARG, "n_outer exceeds 4096");
     if (!c->have_state) return fail(c, DEBLUR_E_STATE, "deblur_init must come first");
@@ -1175,7 +1210,7 @@ int deblur_time_kernels(deblur_ctx* c, int32_t reps, float* ms) {
         HIP_TRY(c, hipEventRecord(ev[2], c->stream));
         col_Ht(c, c->stream);
         HIP_TRY(c, hipEventRecord(ev[3], c->stream));
-        row_update(c, c->stream, c->x[par], c->x[1 - par]);
+        row_update(c, c->stream, c->x[par], c->x[1 - par], step_beta(c, 1, 10));
         HIP_TRY(c, hipEventRecord(ev[4], c->stream));
         HIP_TRY(c, hipEventSynchronize(ev[4]));
         par = 1 - par;
@@ -1397,6 +1432,8 @@ struct deblur_cnn {
     double* loss_part = nullptr;
     size_t max_loss_parts = 0;
     int step = 0;
+    bool fista = false;           // Local-Solver: FISTA (else projected gradient)
+    float* wbuf = nullptr;        // FISTA: the last projected-gradient point w_j per tile frame
     std::vector<void*> allocs;
 };
 

@@ -687,12 +687,18 @@ constexpr int kSeg = 8;
 //          c + 1.  Writes the new x frame.
 // Phase 3: each wave re-reads its rows of the new x (an L2 hit) and, per mask
 //          k, does the forward row FFT and the transposed store of Z_k.
-template <int N, int WV>
+//
+// FISTA (accelerated Local-Solver): xc holds the gradient point y_j, the
+// projected step gives w_j, which is stored in wb, and the next gradient
+// point y_{j+1} = w_j + beta (w_j - w_{j-1}) (w_{j-1} read from wb) is
+// written to xn and transformed in phase 3.  beta = 0 makes y_{j+1} = w_j.
+template <int N, int WV, bool FISTA = false>
 __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
         const float2* __restrict__ Gk, const float* __restrict__ xc, const float* __restrict__ u,
         const TileInfo* __restrict__ tiles, const float* __restrict__ tentX, const float* __restrict__ omY,
         const float* __restrict__ omX, const float* __restrict__ tau, SolveParams P,
-        const float2* __restrict__ twg, float* __restrict__ xn, float2* __restrict__ Zk, int t0) {
+        const float2* __restrict__ twg, float* __restrict__ xn, float2* __restrict__ Zk, int t0,
+        float beta, float* __restrict__ wb) {
     using C = Cfg<N, WV>;
     constexpr int n = C::n;
     static_assert(C::RB * N * sizeof(float) <= C::RB * C::LSR * sizeof(float2), "LDS view too small");
@@ -742,6 +748,8 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
         const float* xt = xc + (size_t)t * N * N;
         const float* ut = u + (size_t)t * N * N;
         float* xo = xn + (size_t)t * N * N;
+        float* wt = nullptr;
+        if constexpr (FISTA) wt = wb + (size_t)t * N * N;
         const float tt = tau[t];
         const float* oy = omY + (size_t)ti.ty * N;
         const float* ox = omX + (size_t)ti.tx * N;
@@ -760,7 +768,9 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
             constexpr int OWN = kLanes - 2;
             constexpr int NCG = (N + OWN - 1) / OWN;
             constexpr int NTASK = NCG * SEGS;
-            auto load = [&](int task, float (&X)[kSeg + 2], float (&U)[kSeg]) {
+            // U holds u on the task's rows, then (FISTA) the previous w_{j-1}
+            constexpr int UN = FISTA ? 2 * kSeg : kSeg;
+            auto load = [&](int task, float (&X)[kSeg + 2], float (&U)[UN]) {
                 const int c = (task % NCG) * OWN - 1 + lane;
                 const int ia = i0 + (task / NCG) * kSeg;
                 const bool colin = c >= 0 && c < sx;
@@ -771,8 +781,13 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                 }
 #pragma unroll
                 for (int k = 0; k < kSeg; ++k) U[k] = (colin && ia + k < sy) ? ut[(ia + k) * N + c] : 0.f;
+                if constexpr (FISTA) {
+#pragma unroll
+                    for (int k = 0; k < kSeg; ++k)
+                        U[kSeg + k] = (colin && ia + k < sy) ? wt[(ia + k) * N + c] : 0.f;
+                }
             };
-            auto update = [&](int task, const float (&X)[kSeg + 2], const float (&U)[kSeg]) {
+            auto update = [&](int task, const float (&X)[kSeg + 2], const float (&U)[UN]) {
                 const int c = (task % NCG) * OWN - 1 + lane;
                 const int ia = i0 + (task / NCG) * kSeg;
                 const bool colin = c >= 0 && c < sx;
@@ -809,10 +824,17 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                         if (P.positivity) val = fmaxf(val, 0.f);
                     }
                     qv_up = qv;
-                    if (lane >= 1 && lane <= OWN && c < N) xo[i * N + c] = val;
+                    if (lane >= 1 && lane <= OWN && c < N) {
+                        if constexpr (FISTA) {
+                            wt[i * N + c] = val;
+                            xo[i * N + c] = beta != 0.f ? val + beta * (val - U[kSeg + k]) : val;
+                        } else {
+                            xo[i * N + c] = val;
+                        }
+                    }
                 }
             };
-            float XA[kSeg + 2], UA[kSeg], XB[kSeg + 2], UB[kSeg], XC[kSeg + 2], UC[kSeg];
+            float XA[kSeg + 2], UA[UN], XB[kSeg + 2], UB[UN], XC[kSeg + 2], UC[UN];
             constexpr int S = C::W;   // task stride of a wave
             if (wave < NTASK) load(wave, XA, UA);
             if (wave + S < NTASK) load(wave + S, XB, UB);
@@ -899,7 +921,13 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                         val = xm - tt * grad;
                         if (P.positivity) val = fmaxf(val, 0.f);
                     }
-                    xo[(size_t)i * N + c] = val;
+                    if constexpr (FISTA) {
+                        const float wp = wt[(size_t)i * N + c];   // 0 outside the support
+                        wt[(size_t)i * N + c] = val;
+                        xo[(size_t)i * N + c] = beta != 0.f ? val + beta * (val - wp) : val;
+                    } else {
+                        xo[(size_t)i * N + c] = val;
+                    }
                 }
             }
         }

@@ -39,7 +39,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _one_round_map(name, frame, sampled, rounds_before, plan=None):
+def _one_round_map(name, frame, sampled, rounds_before, plan=None, local_solver="pg"):
     """One-step map parity: the GPU state after ``rounds_before`` graph-captured
     D-R rounds is fed to the FP64 oracle, which runs one more round (n_inner
     Local-Solver steps + consensus + dual update, Algorithm 1) on the sampled
@@ -66,7 +66,8 @@ def _one_round_map(name, frame, sampled, rounds_before, plan=None):
     y, W = y.astype(np.float64), W.astype(np.float64)
     prob = Problem(L, psfs, y, W, lam=w.lam, reg_param=w.eps, gamma=w.gamma, rho=w.rho, operator=F)
     params = dl.make_params(w.M, w.tiles, w.pitch, w.overlap, w.grid, w.psf_size, lam=w.lam, reg_param=w.eps,
-                            gamma=w.gamma, rho=w.rho)
+                            gamma=w.gamma, rho=w.rho,
+                            local_solver=dl.SOLVER_FISTA if local_solver == "fista" else dl.SOLVER_PG)
     ctx = dl.Context(params, psfs)
     assert ctx.tiles[0].frame == frame
     if plan:
@@ -89,7 +90,7 @@ def _one_round_map(name, frame, sampled, rounds_before, plan=None):
     for t in need:
         ref_tau = solver.step_size(prob, t)
         assert abs(tau[t] - ref_tau) <= 1e-5 * ref_tau
-        xs[t] = solver.local_solve(prob, t, xk[t], uk[t], w.n_inner, float(tau[t]))
+        xs[t] = solver.local_solve(prob, t, xk[t], uk[t], w.n_inner, float(tau[t]), local_solver)
         v[t] = 2.0 * xs[t] - uk[t]
     zbar, _ = solver.consensus_average(prob, v)
     for t in sampled:
@@ -113,6 +114,13 @@ def test_batched_workload_one_round_map_on_sampled_tiles():
     _one_round_map("batched", 320, [0, 4 * 8 + 5], 3,
                    plan=dict(col_waves=2, row_waves=2, tile_order=2, tile_groups=2))
     _one_round_map("batched", 320, [3, 63], 1, plan=dict(col_waves=2, row_waves=2, tile_order=0, tile_groups=4))
+
+
+def test_batched_workload_fista_round_on_sampled_tiles():
+    """The FISTA Local-Solver at full size: one round of 10 accelerated steps
+    on the batched workload, in the benchmark's launch shapes."""
+    _one_round_map("batched", 320, [0, 4 * 8 + 5, 63], 2, local_solver="fista",
+                   plan=dict(col_waves=2, row_waves=2, tile_order=2, tile_groups=4))
 
 
 def test_large_workload_one_round_map_on_sampled_tiles():
