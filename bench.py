@@ -104,6 +104,21 @@ def build_workload(name="batched", tune=True, plan=None):
     return ctx, w, scene, psfs, y, W, trials
 
 
+def fista_context(ctx, psfs, y, W):
+    """A second context on the same workload, observation and launch plan,
+    with the FISTA Local-Solver."""
+    import torch
+    from paper_1705_06603_amd import _lib as dl
+    params = dl.Params.from_buffer_copy(ctx.params)
+    params.local_solver = dl.SOLVER_FISTA
+    params.fft_size = ctx.tiles[0].frame
+    fctx = dl.Context(params, psfs)
+    fctx.set_plan(ctx.plan())
+    fctx.set_observation(torch.tensor(y.astype(np.float32), device="cuda"),
+                         torch.tensor(W.astype(np.float32), device="cuda"))
+    return fctx
+
+
 def tile_bytes(ctx):
     """Compulsory bytes per launch of each kernel: every input read once,
     every output written once, each PSF node spectrum read once.
@@ -242,7 +257,7 @@ def schedule_iterations(w, rounds, growth):
     return sum(w.n_inner + growth * k for k in range(rounds))
 
 
-def convergence(ctx, w, args):
+def convergence(ctx, w, args, fctx=None):
     """Time and iterations to a D-R residual of 1e-4 from the plain start and
     from the network's warm start (with per-tile fallback), same GPU, same
     scene.  The network is trained first (untimed) on plain-solver pairs of
@@ -273,9 +288,12 @@ def convergence(ctx, w, args):
                         "seconds": round(train_s, 2)}}
     stream = torch.cuda.current_stream()
     # plain and warm start with the fixed schedule; plain start with the
-    # paper's growing schedule (n_inner + n_inner k steps in round k)
-    for label in ("plain", "warm", "plain_growing"):
+    # paper's growing schedule (n_inner + n_inner k steps in round k); plain
+    # start with the FISTA Local-Solver
+    labels = ("plain", "warm", "plain_growing") + (("plain_fista",) if fctx is not None else ())
+    for label in labels:
         growth = w.n_inner if label == "plain_growing" else 0
+        c = fctx if label == "plain_fista" else ctx
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -283,9 +301,9 @@ def convergence(ctx, w, args):
         if label == "warm":
             _, nf = ctx.init_cnn(net)
         else:
-            ctx.init()
+            c.init()
             nf = None
-        res = run_to_tolerance(ctx, w, 1e-4, args.max_rounds if not growth else 60, label,
+        res = run_to_tolerance(c, w, 1e-4, args.max_rounds if not growth else 60, label,
                                chunk=100 if not growth else 5, growth=growth)
         e1.record(stream)
         torch.cuda.synchronize()
@@ -422,8 +440,33 @@ def main():
                            "best": best.as_dict(), "default": dflt.as_dict(),
                            "worst_us_per_iter": round(max(t.us_per_iter for t in trials), 2)}
     if not args.no_convergence:
-        print("# convergence: plain vs warm start", file=sys.stderr, flush=True)
-        out["convergence"] = convergence(ctx, w, args)
+        # the FISTA Local-Solver on the same workload and plan: its step
+        # throughput (same timed solve as above) and, below, its time to 1e-4
+        print("# FISTA Local-Solver", file=sys.stderr, flush=True)
+        fctx = fista_context(ctx, psfs, y, W)
+
+        def fstep():
+            fctx.init()
+            fctx.run(n_outer, n_inner)
+            fctx.assemble()
+
+        fstep()
+        torch.cuda.synchronize()
+        f0 = torch.cuda.Event(enable_timing=True)
+        f1 = torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        for _ in range(args.steps):
+            fstep()
+        f1.record(stream)
+        torch.cuda.synchronize()
+        fms = f0.elapsed_time(f1) / args.steps
+        fk = fctx.time_kernels(reps=20)
+        out["fista"] = {"ms_per_step": round(fms, 3),
+                        "value": round((w.M * w.M) * iters / (fms * 1e-3) / 1e6, 2), "unit": UNIT,
+                        "row_update_ms": round(fk["row_update"], 5)}
+        print("# convergence: plain vs warm start vs FISTA", file=sys.stderr, flush=True)
+        out["convergence"] = convergence(ctx, w, args, fctx)
+        fctx.close()
     if pool is not None:
         print(f"# cpu baseline ({procs} processes)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(pool, procs, psfs, y, W, w, args.cpu_budget)
