@@ -93,3 +93,24 @@ def test_fista_rejects_the_growing_schedule():
         ctx.run(2, 2, growth=2)
     assert e.value.code == -1
     ctx.close()
+
+
+def test_fista_context_warm_start_matches_projected_gradient_context():
+    """The warm-start judge takes one step with no momentum, so a FISTA
+    context keeps the same tiles and starts from the same state."""
+    from paper_1705_06603_amd import _lib as dl
+    from tests._gpu import context_of
+    from tests.test_gpu_cnn import _params
+    prob = _mid_problem(seed=17)
+    out = []
+    for m in ("pg", "fista"):
+        ctx = context_of(prob, local_solver=m)
+        N = ctx.tiles[0].frame
+        net = dl.Net(ctx.n_tiles, N, N, params=_params(21))
+        use, nf = ctx.init_cnn(net)
+        x, u = ctx.get_state()
+        out.append((use.copy(), nf, x.cpu().numpy(), u.cpu().numpy()))
+        net.close()
+        ctx.close()
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+    assert np.array_equal(out[0][2], out[1][2]) and np.array_equal(out[0][3], out[1][3])
