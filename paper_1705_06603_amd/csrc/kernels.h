@@ -341,6 +341,16 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_inv(const float2* __re
 // the first two orders).
 enum { kOrderColumnMajor = 0, kOrderTileMajor = 1, kOrderHeavyFirst = 2 };
 
+// Per-lane part of a column slot position: element (q, g) of slot s in
+// layout L_R lies at slot_base(lane, ls) + slot_const<N, R>(s) for lines of
+// stride ls, so a wave's loads and stores of one transform share one lane
+// pointer and differ by compile-time (immediate) offsets.
+template <int N>
+__device__ __forceinline__ int slot_base(int lane, int ls) {
+    constexpr int LPL = lanes_per_line<N>();
+    return (lane / LPL) * ls + (lane % LPL);
+}
+
 struct ColItem {
     int t;        // tile of this wave
     int f0;       // first packed column of this wave (0 for a Nyquist wave)
@@ -407,6 +417,22 @@ __device__ __forceinline__ void col_out(float2* __restrict__ p, float2 v, int mo
     else if (line == 0) reinterpret_cast<float*>(p)[1] = v.x;
 }
 
+// Stores a wave's transformed columns (layout L_{nat radix}) from the lane
+// pointer of slot_base; ordinary waves (special == false, every lane mode 0)
+// store whole complex values without selects.
+template <int N>
+__device__ __forceinline__ void store_col(float2* __restrict__ pl, const float2 (&v)[kV], bool special, int mode,
+                                          int line) {
+    constexpr int R = nat_radix<N>();
+    if (special) {
+#pragma unroll
+        for (int s = 0; s < kV; ++s) col_out(pl + slot_const<N, R>(s), v[s], mode, line);
+    } else {
+#pragma unroll
+        for (int s = 0; s < kV; ++s) pl[slot_const<N, R>(s)] = v[s];
+    }
+}
+
 // Loads the spectrum values of one term for the wave's columns, in the
 // forward transform's output layout: column f0 + line, or column N/2 on
 // every line of a Nyquist wave.
@@ -415,12 +441,9 @@ __device__ __forceinline__ void load_spec(float2 (&sp)[kV], const float2* __rest
                                           int lane) {
     constexpr int RL = last_radix<N, kFwd>();
     const int c0 = it.nyq ? N / 2 : it.f0, ls = it.nyq ? 0 : N;
+    const float2* __restrict__ bl = base + (size_t)c0 * N + slot_base<N>(lane, ls);
 #pragma unroll
-    for (int s = 0; s < kV; ++s) {
-        int q, g;
-        slot_pos<N, RL>(lane, s, q, g);
-        sp[s] = base[(size_t)c0 * N + q * ls + g];
-    }
+    for (int s = 0; s < kV; ++s) sp[s] = bl[slot_const<N, RL>(s)];
 }
 
 // H: Yc[f][:] = IFFT_col( sum_{ky,kx} spec_k . FFT_col(a_ky . Z_kx[f][:]) )
@@ -440,6 +463,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_H(const float2* __rest
     if (!it.valid) return;
     const int t = it.t, line = lane / LPL, mode = col_mode(it, line);
     const int ls = it.nyq ? 0 : N;    // a Nyquist wave reads column 0 on every line
+    const bool special = it.nyq || it.f0 == 0;   // wave-uniform: some lane has mode != 0
     const TileInfo* tp = tiles + t;
     const int nky = tp->nky, nkx = tp->nkx, ty = tp->ty;
     const int nterm = nky * nkx;
@@ -455,11 +479,20 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_H(const float2* __rest
         float2 v[kV];
         {
             const int ln = fresh_lane(lane);
+            const float2* __restrict__ zl = zt + slot_base<N>(ln, ls);
+            const float* __restrict__ al = am + ln % LPL;
+            if (special) {
 #pragma unroll
-            for (int s = 0; s < kV; ++s) {
-                int q, g;
-                slot_pos<N, nat_radix<N>()>(ln, s, q, g);
-                v[s] = cscale(col_in(zt[q * ls + g], mode), am[g]);
+                for (int s = 0; s < kV; ++s) {
+                    constexpr int R = nat_radix<N>();
+                    v[s] = cscale(col_in(zl[slot_const<N, R>(s)], mode), al[slot_const<N, R>(s)]);
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < kV; ++s) {
+                    constexpr int R = nat_radix<N>();
+                    v[s] = cscale(zl[slot_const<N, R>(s)], al[slot_const<N, R>(s)]);
+                }
             }
         }
         fft_passes<N, kFwd>(v, sw, tw, lane);
@@ -468,13 +501,8 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_H(const float2* __rest
         for (int s = 0; s < kV; ++s) acc[s] = cadd(acc[s], cmul(sp[s], v[s]));
     }
     fft_passes<N, kInv>(acc, sw, tw + C::TWC_F, lane);
-    float2* yt = Yc + (size_t)t * C::SPEC + (size_t)it.f0 * N;
-#pragma unroll
-    for (int s = 0; s < kV; ++s) {
-        int q, g;
-        slot_pos<N, nat_radix<N>()>(lane, s, q, g);
-        col_out(yt + q * ls + g, acc[s], mode, q);
-    }
+    float2* __restrict__ yl = Yc + (size_t)t * C::SPEC + (size_t)it.f0 * N + slot_base<N>(lane, ls);
+    store_col<N>(yl, acc, special, mode, line);
 }
 
 // H^T: Gk[kx][f][:] = sum_ky a_ky . IFFT_col( conj(spec_k) . FFT_col(Rr[f][:]) )
@@ -494,19 +522,16 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_Ht(const float2* __res
     if (!it.valid) return;
     const int t = it.t, line = lane / LPL, mode = col_mode(it, line);
     const int ls = it.nyq ? 0 : N;
+    const bool special = it.nyq || it.f0 == 0;   // wave-uniform: some lane has mode != 0
     const TileInfo* tp = tiles + t;
     const int nky = tp->nky, nkx = tp->nkx, ty = tp->ty;
     const int nterm = nky * nkx;
     float2* sw = lds + wave * (C::LwC * C::LSC + kLinePad);
     float2 S[kV], sp[kV], acc[kV];
     {
-        const float2* rt = Rr + (size_t)t * C::SPEC + (size_t)it.f0 * N;
+        const float2* __restrict__ rl = Rr + (size_t)t * C::SPEC + (size_t)it.f0 * N + slot_base<N>(lane, ls);
 #pragma unroll
-        for (int s = 0; s < kV; ++s) {
-            int q, g;
-            slot_pos<N, nat_radix<N>()>(lane, s, q, g);
-            S[s] = col_in(rt[q * ls + g], mode);
-        }
+        for (int s = 0; s < kV; ++s) S[s] = col_in(rl[slot_const<N, nat_radix<N>()>(s)], mode);
     }
     fft_passes<N, kFwd>(S, sw, tw, lane);
     for (int term = 0; term < nterm; ++term) {
@@ -523,22 +548,14 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_Ht(const float2* __res
         const float* am = tentY + ((size_t)ty * kMaxK + ky) * N;
         {
             const int ln = fresh_lane(lane);
+            const float* __restrict__ al = am + ln % LPL;
 #pragma unroll
-            for (int s = 0; s < kV; ++s) {
-                int q, g;
-                slot_pos<N, nat_radix<N>()>(ln, s, q, g);
-                acc[s] = cadd(acc[s], cscale(v[s], am[g]));
-            }
+            for (int s = 0; s < kV; ++s) acc[s] = cadd(acc[s], cscale(v[s], al[slot_const<N, nat_radix<N>()>(s)]));
         }
         if (ky == nky - 1) {
-            float2* gt = Gk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)it.f0 * N;
             const int ln = fresh_lane(lane);
-#pragma unroll
-            for (int s = 0; s < kV; ++s) {
-                int q, g;
-                slot_pos<N, nat_radix<N>()>(ln, s, q, g);
-                col_out(gt + q * ls + g, acc[s], mode, q);
-            }
+            float2* __restrict__ gl = Gk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)it.f0 * N + slot_base<N>(ln, ls);
+            store_col<N>(gl, acc, special, mode, line);
         }
     }
 }
