@@ -93,23 +93,30 @@ __device__ __forceinline__ void store_spectrum_T(const float2* __restrict__ sbuf
                                                  float2* __restrict__ out, int i0, int tid_in) {
     using C = Cfg<N, WV>;
     constexpr int n = C::n;
+    // element e = tid + k NT is (row, f) = (e mod RB, e / RB): the row is the
+    // thread's own and f advances by FS = NT / RB per step
+    static_assert(C::NT % C::RB == 0 && n % (C::NT / C::RB) == 0, "transpose does not tile");
+    constexpr int FS = C::NT / C::RB;
     const int tid = fresh_lane(tid_in);
+    const int row = tid % C::RB, f0 = tid / C::RB;
+    const float2* __restrict__ zl = sbuf + line_off<n>(row);
+    float2* __restrict__ ol = out + (size_t)f0 * N + i0 + row;
 #pragma unroll 4
-    for (int e = tid; e < C::RB * n; e += C::NT) {
-        const int row = e % C::RB, f = e / C::RB;
-        const float2 Z = sbuf[line_off<n>(row) + f];
+    for (int k = 0; k < n / FS; ++k) {
+        const int f = f0 + k * FS;
+        const float2 Z = zl[f];
         float2 P;
         if (f == 0) {
             P = make_float2(Z.x + Z.y, Z.x - Z.y);
         } else {
-            const float2 Zm = sbuf[line_off<n>(row) + (n - f)];
+            const float2 Zm = zl[n - f];
             // X = (Z + conj Zm)/2 - i W_N^f (Z - conj Zm)/2
             const float2 A = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
             const float2 B = make_float2(0.5f * (Z.x - Zm.x), 0.5f * (Z.y + Zm.y));
             const float2 wB = cmul(tw[C::RPOST + f], B);
             P = make_float2(A.x + wB.y, A.y - wB.x);
         }
-        out[(size_t)f * N + i0 + row] = P;
+        ol[(size_t)k * FS * N] = P;
     }
 }
 
@@ -123,25 +130,31 @@ __device__ __forceinline__ void load_c2r_T(float2* __restrict__ sbuf, const floa
                                            const float2* __restrict__ tw, int i0, int tid_in) {
     using C = Cfg<N, WV>;
     constexpr int n = C::n;
+    // pair e = tid + k NT is (row, f) = (e mod RB, e / RB), f = f0 + k FS, for
+    // f = 0 .. n/2 (see store_spectrum_T)
+    static_assert(C::NT % C::RB == 0, "transpose does not tile");
+    constexpr int FS = C::NT / C::RB;
     const int tid = fresh_lane(tid_in);
     constexpr int PAIRS = C::RB * (n / 2 + 1);
     constexpr int PER = (PAIRS + C::NT - 1) / C::NT;
+    const int row = tid % C::RB, f0 = tid / C::RB;
+    const float2* __restrict__ pa = in + (size_t)f0 * N + i0 + row;         // column f
+    const float2* __restrict__ pb = in + (size_t)(n - f0) * N + i0 + row;   // column n - f (f >= 1)
     float2 xa[PER], xb[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int e = tid + k * C::NT;
-        if (e < PAIRS) {
-            const int row = e % C::RB, f = e / C::RB;
-            xa[k] = in[(size_t)f * N + i0 + row];
-            xb[k] = in[(size_t)((n - f) % n) * N + i0 + row];
+        const int f = f0 + k * FS;
+        if (f <= n / 2) {
+            const float2* qa = pa + (size_t)k * FS * N;
+            xa[k] = *qa;
+            xb[k] = f == 0 ? *qa : *(pb - (size_t)k * FS * N);   // column (n - f) mod n
         }
     }
+    float2* __restrict__ line = sbuf + line_off<n>(row);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int e = tid + k * C::NT;
-        if (e < PAIRS) {
-            const int row = e % C::RB, f = e / C::RB;
-            float2* line = sbuf + line_off<n>(row);
+        const int f = f0 + k * FS;
+        if (f <= n / 2) {
             if (f == 0) {
                 const float2 X = xa[k];
                 line[0] = make_float2(0.5f * (X.x + X.y), 0.5f * (X.x - X.y));
