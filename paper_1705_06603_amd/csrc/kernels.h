@@ -86,6 +86,22 @@ template <int N, int WV = waves_hi<N>()> struct Cfg {
 // Row transforms (workgroup level)
 // ---------------------------------------------------------------------------
 
+// Row transforms hold slot s of lane l at row l / LPL, complex element
+// l mod LPL + slot_const(s) (natural radix layout).  rslot_base is the float
+// offset of a lane's first slot in a row-major [rows][N] float frame; slot s
+// adds rslot_off(s) floats, a compile-time (immediate) offset.
+template <int N>
+__device__ __forceinline__ int rslot_base(int lane) {
+    constexpr int LPL = lanes_per_line<N / 2>();
+    return (lane / LPL) * N + 2 * (lane % LPL);
+}
+template <int N>
+__device__ __forceinline__ int rslot_tent(int lane) {   // the same offset within one row
+    return 2 * (lane % lanes_per_line<N / 2>());
+}
+template <int N>
+constexpr int rslot_off(int s) { return 2 * slot_const<N / 2, nat_radix<N / 2>()>(s); }
+
 // Transposed store of the WG's rows (natural-order row FFTs of the packed
 // real rows, in sbuf) as packed half-spectra out[f][i0 + row].
 template <int N, int WV>
@@ -250,23 +266,20 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_fwd(const float* __res
     const int kstride = masked ? kMaxK : 1;
     const float* xt = x + (size_t)t * N * N;
     float2 xv[kV];
+    {
+        const float* __restrict__ xl = xt + (size_t)(i0 + wave * C::LwR) * N + rslot_base<N>(lane);
 #pragma unroll
-    for (int s = 0; s < kV; ++s) {
-        int q, m;
-        slot_pos<n, nat_radix<n>()>(lane, s, q, m);
-        const int row = i0 + wave * C::LwR + q;
-        xv[s] = *reinterpret_cast<const float2*>(xt + (size_t)row * N + 2 * m);
+        for (int s = 0; s < kV; ++s) xv[s] = *reinterpret_cast<const float2*>(xl + rslot_off<N>(s));
     }
     __syncthreads();
     float2* sw = sbuf + line_off<C::n>(wave * C::LwR);
     for (int k = 0; k < nk; ++k) {
         float2 v[kV];
-        const float* bm = tentX + ((size_t)ti.tx * kMaxK + k) * N;
+        const float* __restrict__ bl = tentX + ((size_t)ti.tx * kMaxK + k) * N + rslot_tent<N>(lane);
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
-            int q, m;
-            slot_pos<n, nat_radix<n>()>(lane, s, q, m);
-            v[s] = masked ? make_float2(bm[2 * m] * xv[s].x, bm[2 * m + 1] * xv[s].y) : xv[s];
+            const float* b = bl + rslot_off<N>(s);
+            v[s] = masked ? make_float2(b[0] * xv[s].x, b[1] * xv[s].y) : xv[s];
         }
         row_fft_wave<N>(v, sw, tw, lane);
         __syncthreads();
@@ -301,27 +314,20 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_inv(const float2* __re
         __syncthreads();
         float2 v[kV];
         row_c2r_ready<N>(v, sw, tw, lane);
-        const float* bm = tentX + ((size_t)ti.tx * kMaxK + k) * N;
+        const float* __restrict__ bl = tentX + ((size_t)ti.tx * kMaxK + k) * N + rslot_tent<N>(lane);
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
-            int q, m;
-            slot_pos<n, nat_radix<n>()>(lane, s, q, m);
             if (masked) {
-                acc[s].x += bm[2 * m] * v[s].x;
-                acc[s].y += bm[2 * m + 1] * v[s].y;
+                acc[s].x += bl[rslot_off<N>(s)] * v[s].x;
+                acc[s].y += bl[rslot_off<N>(s) + 1] * v[s].y;
             } else {
                 acc[s] = v[s];
             }
         }
     }
-    float* ot = out + (size_t)t * N * N;
+    float* __restrict__ ol = out + (size_t)t * N * N + (size_t)(i0 + wave * C::LwR) * N + rslot_base<N>(lane);
 #pragma unroll
-    for (int s = 0; s < kV; ++s) {
-        int q, m;
-        slot_pos<n, nat_radix<n>()>(lane, s, q, m);
-        const int row = i0 + wave * C::LwR + q;
-        *reinterpret_cast<float2*>(ot + (size_t)row * N + 2 * m) = acc[s];
-    }
+    for (int s = 0; s < kV; ++s) *reinterpret_cast<float2*>(ol + rslot_off<N>(s)) = acc[s];
 }
 
 // ---------------------------------------------------------------------------
@@ -659,14 +665,12 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_resid(const float2* __
     float2* sw = sbuf + line_off<C::n>(wave * C::LwR);
     float2 v[kV];
     row_c2r_ready<N>(v, sw, tw, lane);
-    const float4* ywt = reinterpret_cast<const float4*>(yw + (size_t)t * N * N);
+    // (y, W) pairs of pixels (2m, 2m + 1) as one float4, at float2 offset row N + 2m
+    const float2* __restrict__ yl = yw + (size_t)t * N * N + (size_t)(i0 + wave * C::LwR) * N + rslot_base<N>(lane);
     float obj = 0.f;
 #pragma unroll
     for (int s = 0; s < kV; ++s) {
-        int q, m;
-        slot_pos<n, nat_radix<n>()>(lane, s, q, m);
-        const int row = i0 + wave * C::LwR + q;
-        const float4 o = ywt[((size_t)row * N + 2 * m) >> 1];   // (y0, W0, y1, W1)
+        const float4 o = *reinterpret_cast<const float4*>(yl + rslot_off<N>(s));   // (y0, W0, y1, W1)
         const float d0 = v[s].x - o.x, d1 = v[s].y - o.z;
         const float r0 = o.y * d0, r1 = o.w * d1;
         obj += r0 * d0 + r1 * d1;
@@ -753,22 +757,19 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
             __syncthreads();
             float2 v[kV];
             row_c2r_ready<N>(v, sw, tw, lane);
-            const float* bm = tentX + ((size_t)ti.tx * kMaxK + kx) * N;
+            const float* __restrict__ bl = tentX + ((size_t)ti.tx * kMaxK + kx) * N + rslot_tent<N>(lane);
 #pragma unroll
             for (int s = 0; s < kV; ++s) {
-                int q, m;
-                slot_pos<n, nat_radix<n>()>(lane, s, q, m);
-                const float2 b = *reinterpret_cast<const float2*>(bm + 2 * m);
+                const float2 b = *reinterpret_cast<const float2*>(bl + rslot_off<N>(s));
                 gd[s].x += b.x * v[s].x;
                 gd[s].y += b.y * v[s].y;
             }
         }
         __syncthreads();
+        {
+            float* gl = sg + wave * C::LwR * N + rslot_base<N>(lane);
 #pragma unroll
-        for (int s = 0; s < kV; ++s) {
-            int q, m;
-            slot_pos<n, nat_radix<n>()>(lane, s, q, m);
-            *reinterpret_cast<float2*>(sg + (wave * C::LwR + q) * N + 2 * m) = gd[s];
+            for (int s = 0; s < kV; ++s) *reinterpret_cast<float2*>(gl + rslot_off<N>(s)) = gd[s];
         }
         __syncthreads();
     }
@@ -804,22 +805,30 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                 const int c = (task % NCG) * OWN - 1 + lane;
                 const int ia = i0 + (task / NCG) * kSeg;
                 const bool colin = c >= 0 && c < sx;
+                // column c from row ia: row ia + j at a compile-time offset j N
+                const size_t o = (size_t)ia * N + c;
+                const float* __restrict__ xs = xt + o;
+                const float* __restrict__ us = ut + o;
 #pragma unroll
                 for (int j = 0; j < kSeg + 2; ++j) {
                     const int rr = ia - 1 + j;
-                    X[j] = (colin && rr >= 0 && rr < sy) ? xt[rr * N + c] : 0.f;
+                    X[j] = (colin && rr >= 0 && rr < sy) ? xs[(j - 1) * N] : 0.f;
                 }
 #pragma unroll
-                for (int k = 0; k < kSeg; ++k) U[k] = (colin && ia + k < sy) ? ut[(ia + k) * N + c] : 0.f;
+                for (int k = 0; k < kSeg; ++k) U[k] = (colin && ia + k < sy) ? us[k * N] : 0.f;
                 if constexpr (FISTA) {
+                    const float* __restrict__ ws = wt + o;
 #pragma unroll
-                    for (int k = 0; k < kSeg; ++k)
-                        U[kSeg + k] = (colin && ia + k < sy) ? wt[(ia + k) * N + c] : 0.f;
+                    for (int k = 0; k < kSeg; ++k) U[kSeg + k] = (colin && ia + k < sy) ? ws[k * N] : 0.f;
                 }
             };
             auto update = [&](int task, const float (&X)[kSeg + 2], const float (&U)[UN]) {
                 const int c = (task % NCG) * OWN - 1 + lane;
                 const int ia = i0 + (task / NCG) * kSeg;
+                // pixel (ia, c) in the frame and in sg; row ia + k at offset k N
+                const size_t o = (size_t)ia * N + c;
+                const float* sgs = sg + (ia - i0) * N + c;
+                float* __restrict__ xos = xo + o;
                 const bool colin = c >= 0 && c < sx;
                 const bool rin = c + 1 < sx;   // the right neighbour is in the support
                 // vertical flux of the row above the strip
@@ -849,17 +858,17 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                         // -div of the flux (s gh, s gv): backward differences
                         const float g = (qh_l - qh) + (qv_up - qv);
                         const float alpha = P.gamma * oy[i] * oxc;
-                        const float grad = sg[(i - i0) * N + c] + P.lambda * g + alpha * (xm - U[k]);
+                        const float grad = sgs[k * N] + P.lambda * g + alpha * (xm - U[k]);
                         val = xm - tt * grad;
                         if (P.positivity) val = fmaxf(val, 0.f);
                     }
                     qv_up = qv;
                     if (lane >= 1 && lane <= OWN && c < N) {
                         if constexpr (FISTA) {
-                            wt[i * N + c] = val;
-                            xo[i * N + c] = beta != 0.f ? val + beta * (val - U[kSeg + k]) : val;
+                            wt[o + (size_t)k * N] = val;
+                            xos[k * N] = beta != 0.f ? val + beta * (val - U[kSeg + k]) : val;
                         } else {
-                            xo[i * N + c] = val;
+                            xos[k * N] = val;
                         }
                     }
                 }
@@ -971,12 +980,12 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
         const float* bm = tentX + ((size_t)ti.tx * kMaxK + kx) * N;
         float2 v[kV];
         const int ln = fresh_lane(lane);
+        const float* __restrict__ bl = bm + rslot_tent<N>(ln);
+        const float* __restrict__ xl = xw + wave * C::LwR * N + rslot_base<N>(ln);
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
-            int q, m;
-            slot_pos<n, nat_radix<n>()>(ln, s, q, m);
-            const float2 b = *reinterpret_cast<const float2*>(bm + 2 * m);
-            const float2 xv = *reinterpret_cast<const float2*>(xw + (wave * C::LwR + q) * N + 2 * m);
+            const float2 b = *reinterpret_cast<const float2*>(bl + rslot_off<N>(s));
+            const float2 xv = *reinterpret_cast<const float2*>(xl + rslot_off<N>(s));
             v[s] = make_float2(b.x * xv.x, b.y * xv.y);
         }
         __syncthreads();
