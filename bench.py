@@ -160,8 +160,9 @@ def kernel_variant(ctx, kernel):
 
 def measured_traffic(ctx, workload, kernel):
     """HBM bytes per launch of kernel from the committed FETCH_SIZE /
-    WRITE_SIZE counter summary, if it was taken on the current kernel sources
-    and the same launch shape; else None."""
+    WRITE_SIZE counter summary (one entry per launch shape measured), if it
+    was taken on the current kernel sources and the same launch shape; else
+    None."""
     tfile = os.path.join(ROOT, "profiles", f"{workload}_hbm_traffic.json")
     if not os.path.exists(tfile):
         return None
@@ -169,10 +170,14 @@ def measured_traffic(ctx, workload, kernel):
         tj = json.load(fh)
     if tj.get("kernel_source_hash") != kernel_source_hash():
         return None
-    k = tj.get("kernels", {}).get(kernel)
-    if not k or k.get("variant") != kernel_variant(ctx, kernel):
-        return None
-    return k.get("bytes_per_launch")
+    entries = tj.get("kernels", {}).get(kernel) or []
+    if isinstance(entries, dict):
+        entries = [entries]
+    want = kernel_variant(ctx, kernel)
+    for k in entries:
+        if k.get("variant") == want:
+            return k.get("bytes_per_launch")
+    return None
 
 
 def _oracle_tile_steps(job):
