@@ -224,7 +224,9 @@ int deblur_blur_global(deblur_ctx* ctx, const float* x_global, float* y_global);
  * the consensus kernel.  Writes the mean milliseconds per launch to
  * ms_host[DEBLUR_N_KERNELS] in the order col_H, row_resid, col_Ht,
  * row_update, consensus.  The state (x, u) is saved and restored around the
- * measurement. */
+ * measurement.  With the FISTA Local-Solver the steps use the momentum of a
+ * step inside a 10-step run, so row_update is timed with its extra frame
+ * traffic. */
 enum { DEBLUR_N_KERNELS = 5 };
 int deblur_time_kernels(deblur_ctx* ctx, int32_t reps, float* ms_host);
 
