@@ -20,7 +20,9 @@ Modules:
               Algorithm 1, residual and output assembly
   minimiser-- the result oracle: a direct minimiser of the consensus problem
               Eq. (4) for tiny images, and dense closed-form solves
-  cnn      -- the warm-start network (forward / backward, BF16 rounding)
+  cnn      -- the warm-start network (forward / backward, BF16 rounding, Adam)
+  warm     -- the warm start around the network: tile scale and input,
+              network start, and the per-tile gradient-map fallback judge
 
 Parity unpinned: nothing in the deblurring path.  The paper's SNR/SSIM figures
 need its natural test images and are not reproduced.

@@ -67,3 +67,16 @@ def test_adam_first_step_is_signed_learning_rate():
     g = np.array([3.0, -0.5, 1e-3])
     p1, m, v = cnn.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=0.01, eps=0.0)
     assert np.allclose(p1, -0.01 * np.sign(g), rtol=0, atol=1e-15)
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g the bias-corrected moments are exactly g
+    and g^2 at every step, so each step moves by lr g / (|g| + eps): this
+    pins both bias corrections and where eps enters (outside the root)."""
+    g = np.array([2.0, -0.5, 1e-8, -3e-8, 0.0])
+    lr, eps = 0.01, 1e-8
+    w, m, v = np.zeros(5), np.zeros(5), np.zeros(5)
+    for k in range(1, 6):
+        w, m, v = cnn.adam_step(w, g, m, v, k, lr, eps=eps)
+        ref = -k * lr * g / (np.abs(g) + eps)
+        assert np.allclose(w, ref, rtol=1e-12, atol=1e-18), (k, w, ref)
