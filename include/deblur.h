@@ -52,7 +52,9 @@ enum {
     DEBLUR_E_OOM = -3,       /* device allocation failed (create only)    */
     DEBLUR_E_HIP = -4,       /* a HIP runtime call failed                 */
     DEBLUR_E_STATE = -5,     /* call out of order (e.g. no observation)   */
-    DEBLUR_E_NONFINITE = -6  /* a residual or objective was not finite    */
+    DEBLUR_E_NONFINITE = -6  /* a residual or objective was not finite; the
+                                message lists the tiles whose x (else u)
+                                holds a non-finite value                   */
 };
 
 /* Blur model of a tile (Section II-B). */
@@ -124,12 +126,21 @@ typedef struct deblur_tile_desc {
     int32_t n_terms_y, n_terms_x;   /* PSF nodes per axis whose weight touches the support  */
 } deblur_tile_desc;
 
-/* Create a context.  psfs_host: host [G_y][G_x][P][P] fp32, PSF of node
- * (ky, kx) sampled at offsets q in [-r, r]^2 (index q + r); the operator is
- * the true convolution (H x)(j) = sum_q h(q) x(j - q).  stream: a
- * hipStream_t (NULL = default stream).  Validates the geometry (overlap + 2r
- * <= pitch, every block >= P, supports fit the largest frame 640), allocates
- * all device memory, computes the PSF spectra.  *out receives the context. */
+/* Create a context for the distributed problem of Section III-A: the image
+ * split into overlapping blocks (Fig. 1), one local cost f_i per block with
+ * the shift-variant blur of Section II-B (PSFs sampled on a regular grid and
+ * blended by first-order interpolation weights, Eq. (2)).
+ * psfs_host: host [G_y][G_x][P][P] fp32, PSF of node (ky, kx) sampled at
+ * offsets q in [-r, r]^2 (index q + r); the operator is the true convolution
+ * (H x)(j) = sum_q h(q) x(j - q).  Every PSF must be finite, non-negative and
+ * sum to 1 within 1e-4 (the normalised PSFs of Section IV), else DEBLUR_E_ARG
+ * with the offending node in deblur_last_error(NULL): the step sizes below
+ * bound ||H_t||^2 by the largest row sum of H_t, which holds because the
+ * column sums of H_t are at most 1 for such PSFs.  stream: a hipStream_t
+ * (NULL = default stream).  Validates the geometry (overlap + 2r <= pitch,
+ * every block >= P, supports fit the largest frame 640), allocates all
+ * device memory, computes the PSF spectra.  *out receives the context, owned
+ * by the caller until deblur_destroy.  On failure nothing stays allocated. */
 int deblur_create(const deblur_params* params, const float* psfs_host, void* stream,
                   deblur_ctx** out);
 
@@ -139,9 +150,12 @@ void deblur_destroy(deblur_ctx* ctx);
  * on this thread).  Valid until the next call on the same context. */
 const char* deblur_last_error(const deblur_ctx* ctx);
 
-/* Copy up to cap tile descriptors to host memory desc_host; writes the total
- * float counts of support- and block-packed arrays to *support_total and
- * *block_total (either may be NULL).  Returns the number of tiles. */
+/* The blocks y_i and the supports of the unknowns x_i of Section III-A
+ * (Fig. 1: each x_i extends its block by the PSF half-width r on every side).
+ * Copies up to cap tile descriptors to host memory desc_host (may be NULL);
+ * writes the total float counts of support- and block-packed arrays to
+ * *support_total and *block_total (either may be NULL).  Returns the number
+ * of tiles, or DEBLUR_E_ARG for a NULL context. */
 int deblur_tile_layout(const deblur_ctx* ctx, deblur_tile_desc* desc_host, int32_t cap,
                        int64_t* support_total, int64_t* block_total);
 
@@ -198,11 +212,24 @@ int deblur_run(deblur_ctx* ctx, int32_t n_outer, int32_t n_inner, double tol,
 int deblur_run_schedule(deblur_ctx* ctx, int32_t n_outer, int32_t n_inner, int32_t growth, int32_t first_round,
                         double tol, double* residuals_host, int32_t* rounds_done);
 
-/* Checkpoint / restore (x, u), device support-packed arrays. */
-int deblur_get_state(deblur_ctx* ctx, float* x_tiles, float* u_tiles);
-int deblur_set_state(deblur_ctx* ctx, const float* x_tiles, const float* u_tiles);
+/* Checkpoint / restore of Algorithm 1's iterate: the local estimates x_i
+ * and the dual variables u_i (device, support-packed), and the round index k
+ * of the outer loop (the number of consensus steps since the state was set
+ * by deblur_init, deblur_init_cnn or deblur_set_state; deblur_run,
+ * deblur_run_schedule and deblur_consensus advance it).  get: x_tiles,
+ * u_tiles and round_host may each be NULL (only the others are written);
+ * needs a state (DEBLUR_E_STATE).  set: round >= 0 becomes the context's
+ * round index (a caller continuing a growing schedule passes it back as
+ * first_round); needs an observation.  The state fully determines the next
+ * rounds: FISTA restarts its momentum at every round, so nothing else is
+ * carried across a round boundary. */
+int deblur_get_state(deblur_ctx* ctx, float* x_tiles, float* u_tiles, int32_t* round_host);
+int deblur_set_state(deblur_ctx* ctx, const float* x_tiles, const float* u_tiles, int32_t round);
 
-/* Output image x_hat = sum_t omega_t x_t on X: device [M_y + 2r][M_x + 2r]. */
+/* Output of Algorithm 1, returned as the local estimates x_1 ... x_N, merged
+ * into one image with the consensus weights: x_hat = sum_t omega_t x_t on X
+ * (equal to the consensus image zbar at convergence): device
+ * [M_y + 2r][M_x + 2r], written on the context stream.  Needs a state. */
 int deblur_assemble(deblur_ctx* ctx, float* x_global);
 
 /* Objective terms summed over tiles at the current (x, u), host doubles:

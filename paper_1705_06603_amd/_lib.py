@@ -99,8 +99,8 @@ def lib():
         "deblur_consensus": ([vp, dp], i32),
         "deblur_run": ([vp, i32, i32, ctypes.c_double, dp, ctypes.POINTER(i32)], i32),
         "deblur_run_schedule": ([vp, i32, i32, i32, i32, ctypes.c_double, dp, ctypes.POINTER(i32)], i32),
-        "deblur_get_state": ([vp, f32p, f32p], i32),
-        "deblur_set_state": ([vp, f32p, f32p], i32),
+        "deblur_get_state": ([vp, f32p, f32p, ctypes.POINTER(i32)], i32),
+        "deblur_set_state": ([vp, f32p, f32p, i32], i32),
         "deblur_assemble": ([vp, f32p], i32),
         "deblur_objective": ([vp, dp], i32),
         "deblur_step_sizes": ([vp, ctypes.POINTER(ctypes.c_float)], i32),
@@ -266,12 +266,19 @@ class Context:
         return [res[i] for i in range(done.value)]
 
     def get_state(self):
+        """(x, u) support-packed device arrays of the current iterate."""
         x, u = self._empty(self.support_total), self._empty(self.support_total)
-        self._check(self._L.deblur_get_state(self._h, _ptr(x), _ptr(u)))
+        self._check(self._L.deblur_get_state(self._h, _ptr(x), _ptr(u), None))
         return x, u
 
-    def set_state(self, x, u):
-        self._check(self._L.deblur_set_state(self._h, _ptr(x), _ptr(u)))
+    def state_round(self):
+        """Round index k of the current state (consensus steps since it was set)."""
+        k = ctypes.c_int32()
+        self._check(self._L.deblur_get_state(self._h, None, None, ctypes.byref(k)))
+        return k.value
+
+    def set_state(self, x, u, round=0):
+        self._check(self._L.deblur_set_state(self._h, _ptr(x), _ptr(u), round))
 
     def assemble(self):
         out = self._empty(self.X_shape[0] * self.X_shape[1])

@@ -1261,6 +1261,22 @@ __global__ __launch_bounds__(256) void k_block_max(const float* __restrict__ fr,
     if (threadIdx.x == 0) out[t] = bad ? NAN : red[0];
 }
 
+// flag[t] = (1 if frame t of x holds a non-finite value) + (2 if frame t of
+// u does) (one workgroup per tile; an error path only).
+__global__ __launch_bounds__(256) void k_tile_nonfinite(const float* __restrict__ x, const float* __restrict__ u,
+                                                       int N, int* __restrict__ flag) {
+    const int t = blockIdx.x;
+    const size_t base = (size_t)t * N * N;
+    int bx = 0, bu = 0;
+    for (int e = threadIdx.x; e < N * N; e += 256) {
+        bx |= !isfinite(x[base + e]);
+        bu |= !isfinite(u[base + e]);
+    }
+    bx = __syncthreads_or(bx);
+    bu = __syncthreads_or(bu);
+    if (threadIdx.x == 0) flag[t] = (bx ? 1 : 0) + (bu ? 2 : 0);
+}
+
 // Regulariser value and metric term per tile and row block:
 // part[t * gridDim.x + blk] = (sum phi(D x), sum 1/2 alpha (x - u)^2).
 __global__ __launch_bounds__(256) void k_reg_terms(const float* __restrict__ x, const float* __restrict__ u,

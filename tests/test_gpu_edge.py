@@ -113,3 +113,61 @@ def test_error_paths():
     with pytest.raises(dl.DeblurError) as e:
         dl.Context(bad, np.ones((2, 2, 4, 4)) / 16)
     assert e.value.code == -1
+
+
+def test_psf_contract_is_enforced_through_the_gpu_binding():
+    """A PSF that is negative somewhere or does not sum to 1 is rejected at
+    creation (the step sizes assume unit-sum non-negative PSFs)."""
+    from paper_1705_06603_amd import _lib as dl
+    from tests._gpu import params_of
+    prob = _f32_problem(tiny_problem(M=40, T=2, p=20, o=4, P=5, G=2, seed=8))
+    for k, change in ((1, 2.0), (3, -1.0)):
+        psfs = prob.psfs.copy()
+        psfs.reshape(4, 5, 5)[k] *= change
+        with pytest.raises(dl.DeblurError) as e:
+            dl.Context(params_of(prob), psfs)
+        assert e.value.code == -1 and f"node {k}" in str(e.value), str(e.value)
+
+
+def test_state_carries_the_round_index():
+    from paper_1705_06603_amd import _lib as dl
+    from tests._gpu import context_of
+    prob = _f32_problem(tiny_problem(M=40, T=2, p=20, o=4, P=5, G=2, seed=6))
+    ctx = context_of(prob)
+    ctx.init()
+    assert ctx.state_round() == 0
+    ctx.run(3, 2)
+    assert ctx.state_round() == 3
+    ctx.consensus()
+    assert ctx.state_round() == 4
+    x, u = ctx.get_state()
+    ctx.set_state(x, u, round=7)
+    assert ctx.state_round() == 7
+    ctx.run(2, 2, growth=2, first_round=ctx.state_round())
+    assert ctx.state_round() == 9
+    ctx.init()
+    assert ctx.state_round() == 0
+    with pytest.raises(dl.DeblurError) as e:
+        ctx.set_state(x, u, round=-1)
+    assert e.value.code == -1
+    ctx.close()
+
+
+def test_nonfinite_error_names_the_diverged_tile():
+    """A non-finite value planted (from the host) in one tile's x spreads to
+    the neighbours' u through the consensus step; the error names the tile
+    whose x is non-finite."""
+    from paper_1705_06603_amd import _lib as dl
+    from tests._gpu import context_of, to_dev
+    prob = _f32_problem(tiny_problem(M=40, T=2, p=20, o=4, P=5, G=2, seed=7))
+    ctx = context_of(prob)
+    ctx.init()
+    x, u = (a.cpu().numpy() for a in ctx.get_state())
+    d = ctx.tiles[2]
+    x[d.x_offset + 3] = np.nan
+    ctx.set_state(to_dev(x), to_dev(u))
+    with pytest.raises(dl.DeblurError) as e:
+        ctx.run(1, 1)
+    msg = str(e.value)
+    assert e.value.code == -6 and "non-finite x in 1 tile(s): 2 (row 1, column 0)" in msg, msg
+    ctx.close()

@@ -38,7 +38,8 @@ def _run(ctx, x0, u0, rounds=2, n_inner=3):
 
 
 _CRASH = ("a GPU run of this case ended the test process (abort / segmentation fault inside the library "
-          "call, no fault message); the cause is not found, so the case stays off the GPU")
+          "call, no fault message); the cause is not found, so the case stays off the GPU (the autotuner "
+          "leaves the frame-160 one-wave shapes out of its candidates)")
 
 
 @pytest.mark.parametrize("frame", [pytest.param(160, marks=pytest.mark.skip(reason=_CRASH)), 320, 640])
@@ -106,12 +107,19 @@ def test_autotune_picks_the_fastest_measured_plan():
 
 
 def test_autotune_respects_a_fixed_frame():
+    """With a fixed frame the tuner measures exactly that frame's 36 plans
+    and returns the fastest one it measured."""
     from paper_1705_06603_amd import _lib as dl
     from tests._gpu import params_of
     prob = _problem(160)
     best, trials = dl.autotune(params_of(prob, fft_size=320), prob.psfs, n_inner=2, reps=1)
     assert {t.frame for t in trials} == {320} and len(trials) == 36
+    assert len({(t.col_waves, t.row_waves, t.tile_order, t.tile_groups) for t in trials}) == 36
+    assert all(t.us_per_iter > 0 for t in trials)
     assert best.frame == 320
+    assert best.us_per_iter == min(t.us_per_iter for t in trials)
+    assert (best.col_waves, best.row_waves, best.tile_order, best.tile_groups) in {
+        (t.col_waves, t.row_waves, t.tile_order, t.tile_groups) for t in trials}
 
 
 def test_two_tile_groups_eager_steps():

@@ -37,3 +37,45 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def _create_error(psfs, P=3, G=2):
+    """deblur_create on PSFs that break the contract: the check comes before
+    any HIP call, so this runs without a GPU."""
+    from paper_1705_06603_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    import numpy as np
+    L = _lib.lib()
+    params = _lib.make_params(24, 2, 12, 2, G, P)
+    psf = np.ascontiguousarray(psfs, dtype=np.float32)
+    h = ctypes.c_void_p()
+    rc = L.deblur_create(ctypes.byref(params), psf.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(h))
+    assert not h.value
+    return rc, L.deblur_last_error(None).decode()
+
+
+def _unit_psfs(G=2, P=3):
+    import numpy as np
+    rng = np.random.default_rng(0)
+    h = rng.random((G, G, P, P))
+    return h / h.sum(axis=(2, 3), keepdims=True)
+
+
+def test_create_rejects_a_negative_psf():
+    psfs = _unit_psfs()
+    psfs[1, 0, 0, 2] = -0.01
+    psfs[1, 0, 1, 1] += 0.01                 # still sums to 1
+    rc, msg = _create_error(psfs)
+    assert rc == -1 and "negative" in msg and "node 2" in msg, msg
+
+
+def test_create_rejects_a_psf_not_summing_to_one():
+    psfs = _unit_psfs()
+    psfs[0, 1] *= 2.0
+    rc, msg = _create_error(psfs)
+    assert rc == -1 and "sums to 2" in msg and "node 1" in msg, msg
+    psfs = _unit_psfs()
+    psfs[1, 1] *= 1.0 - 2e-4
+    rc, msg = _create_error(psfs)
+    assert rc == -1 and "node 3" in msg, msg
