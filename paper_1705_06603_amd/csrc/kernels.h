@@ -684,6 +684,11 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_resid(const float2* __
     if (tid == 0) obj_part[t * C::RG + blockIdx.x] = 0.5f * tot;
 }
 
+// Projection onto the non-negative orthant. Written as a compare rather than
+// fmaxf so that a NaN (a diverged step) stays NaN, as max(0, NaN) does in the
+// definition, and the non-finite check sees it instead of a clamped 0.
+__device__ __forceinline__ float project_nonneg(float v) { return v < 0.f ? 0.f : v; }
+
 // Scale of the regulariser's derivative for a forward-difference vector g:
 // d phi / d g = s(g) g with s = 1/sqrt(|g|^2 + eps^2) (smoothed TV) or
 // delta / max(|g|, delta) (Huber).
@@ -860,7 +865,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                         const float alpha = P.gamma * oy[i] * oxc;
                         const float grad = sgs[k * N] + P.lambda * g + alpha * (xm - U[k]);
                         val = xm - tt * grad;
-                        if (P.positivity) val = fmaxf(val, 0.f);
+                        if (P.positivity) val = project_nonneg(val);
                     }
                     qv_up = qv;
                     if (lane >= 1 && lane <= OWN && c < N) {
@@ -958,7 +963,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                         const float alpha = P.gamma * oy[i] * oxc;
                         const float grad = sg[(i - i0) * N + c] + P.lambda * g + alpha * (xm - U[h][k]);
                         val = xm - tt * grad;
-                        if (P.positivity) val = fmaxf(val, 0.f);
+                        if (P.positivity) val = project_nonneg(val);
                     }
                     if constexpr (FISTA) {
                         const float wp = wt[(size_t)i * N + c];   // 0 outside the support
