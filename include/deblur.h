@@ -342,6 +342,21 @@ int deblur_autotune(const deblur_params* params, const float* psfs_host, void* s
  *              in [batch][n/2][n] complex -> out [batch][n][n] real. */
 int deblur_debug_fft(int32_t n, int32_t batch, int32_t which, const float* in, float* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * FFT stages as deblur_debug_fft, with the same arguments and results, that
+ * allocate nothing.  The stage tables (twiddles, tile table, tent row) live
+ * in a fixed library-owned device array of 303,872 bytes per GPU, set up on
+ * the first call on each device and held until the process ends; batch is
+ * limited to 4096 frames (larger: DEBLUR_E_ARG, message in
+ * deblur_last_error(NULL)).  The work is enqueued on stream, which must
+ * belong to the current device (else DEBLUR_E_ARG); the call does not wait
+ * for it.  Every call on one GPU rewrites that GPU's array: calls that
+ * overlap on one GPU (different streams, or threads racing on one stream)
+ * race.  Errors: DEBLUR_E_ARG as above, DEBLUR_E_HIP for a failed launch or
+ * symbol lookup. */
+int deblur_debug_fft_noalloc(int32_t n, int32_t batch, int32_t which, const float* in, float* out, void* stream);
+
 
 /* ---------------------------------------------------------------------------
  * Learned warm start.  A 4-layer 3x3 convolutional network (1 -> 32 -> 32 ->

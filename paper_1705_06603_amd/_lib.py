@@ -107,6 +107,7 @@ def lib():
         "deblur_blur_global": ([vp, f32p, f32p], i32),
         "deblur_time_kernels": ([vp, i32, ctypes.POINTER(ctypes.c_float)], i32),
         "deblur_debug_fft": ([i32, i32, i32, f32p, f32p, vp], i32),
+        "deblur_debug_fft_noalloc": ([i32, i32, i32, f32p, f32p, vp], i32),
         "deblur_cnn_create": ([vp, i32, i32, i32, i32, vp, ctypes.POINTER(vp)], i32),
         "deblur_cnn_create_inference": ([vp, i32, i32, i32, i32, vp, ctypes.POINTER(vp)], i32),
         "deblur_cnn_destroy": ([vp], None),
@@ -139,7 +140,7 @@ def exported_symbols():
         "deblur_set_observation", "deblur_apply_H", "deblur_apply_Ht", "deblur_init",
         "deblur_solve_tiles", "deblur_consensus", "deblur_run", "deblur_run_schedule", "deblur_get_state",
         "deblur_set_state", "deblur_assemble", "deblur_objective", "deblur_step_sizes",
-        "deblur_blur_global", "deblur_time_kernels", "deblur_debug_fft",
+        "deblur_blur_global", "deblur_time_kernels", "deblur_debug_fft", "deblur_debug_fft_noalloc",
         "deblur_cnn_create", "deblur_cnn_create_inference", "deblur_cnn_destroy", "deblur_cnn_last_error", "deblur_cnn_get_params",
         "deblur_cnn_set_params", "deblur_cnn_forward", "deblur_cnn_loss_grad", "deblur_cnn_train_step",
         "deblur_cnn_time_forward", "deblur_init_cnn", "deblur_warm_inputs",
@@ -378,18 +379,21 @@ def autotune(params: Params, psfs, n_inner=10, reps=3, stream=None):
     return best, [trials[i] for i in range(min(n.value, cap))]
 
 
-def debug_fft(n, which, data, stream=None):
-    """Runs one FFT stage of the library on a CUDA float32 tensor (see deblur.h)."""
+def debug_fft(n, which, data, stream=None, out=None, noalloc=False):
+    """Runs one FFT stage of the library on a CUDA float32 tensor (see deblur.h).
+    noalloc=True calls deblur_debug_fft_noalloc, which takes its tables from
+    the library's fixed device scratch and does not wait for the stream; out
+    may then be a caller-owned tensor of the stage's output shape."""
     import torch
     L = lib()
     batch = data.shape[0]
-    if which in (0,):
-        out = torch.empty((batch, n // 2, n, 2), dtype=torch.float32, device="cuda")
-    elif which in (1, 2):
-        out = torch.empty((batch, n // 2, n, 2), dtype=torch.float32, device="cuda")
-    else:
-        out = torch.empty((batch, n, n), dtype=torch.float32, device="cuda")
-    rc = L.deblur_debug_fft(n, batch, which, _ptr(data.contiguous()), _ptr(out), _stream_handle(stream))
+    shape = (batch, n, n) if which == 3 else (batch, n // 2, n, 2)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float32, device="cuda")
+    elif tuple(out.shape) != shape:
+        raise ValueError(f"out must have shape {shape}")
+    fn = L.deblur_debug_fft_noalloc if noalloc else L.deblur_debug_fft
+    rc = fn(n, batch, which, _ptr(data.contiguous()), _ptr(out), _stream_handle(stream))
     if rc != 0:
         raise DeblurError(rc, L.deblur_last_error(None).decode())
     return out

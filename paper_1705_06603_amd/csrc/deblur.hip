@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <utility>
@@ -105,6 +106,27 @@ struct Axis {
 };
 
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free FFT stages (deblur_debug_fft_noalloc):
+// the twiddle table of the largest frame, a tile table for up to
+// kNoAllocMaxBatch frames and one tent row. Each GPU holds its own copy until
+// the process ends. In host code `scratch` names a host-side stand-in, never
+// the device memory: host code uses the address hipGetSymbolAddress returns.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kNoAllocMaxBatch = 4096;
+constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kNoAllocTwBytes = round256((size_t)dbl::Cfg<640>::TW_TOTAL * sizeof(float2));
+constexpr size_t kNoAllocTileBytes = round256((size_t)kNoAllocMaxBatch * sizeof(TileInfo));
+constexpr size_t kNoAllocTentBytes = round256((size_t)dbl::kMaxK * 640 * sizeof(float));
+constexpr size_t kNoAllocScratchBytes = kNoAllocTwBytes + kNoAllocTileBytes + kNoAllocTentBytes;
+static_assert(dbl::Cfg<160>::TW_TOTAL <= dbl::Cfg<640>::TW_TOTAL &&
+                  dbl::Cfg<320>::TW_TOTAL <= dbl::Cfg<640>::TW_TOTAL,
+              "the scratch twiddle region holds the largest frame's table");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 struct deblur_ctx {
     deblur_params p{};
@@ -1474,6 +1496,89 @@ int deblur_debug_fft(int32_t n, int32_t batch, int32_t which, const float* in, f
     for (void* p : tmp.allocs) (void)hipFree(p);
     tmp.allocs.clear();
     if (rc) return fail(nullptr, rc, tmp.err);
+    if (e != hipSuccess) return fail(nullptr, DEBLUR_E_HIP, hipGetErrorString(e));
+    return DEBLUR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_dev[kMaxDevices] = {};
+
+// This GPU's copy of `scratch`: its device address is looked up once per
+// device, with that device current, and kept.
+int scratch_address(int dev, unsigned char** out) {
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(nullptr, DEBLUR_E_ARG, "device index " + std::to_string(dev) + " is beyond the " +
+                                               std::to_string(kMaxDevices) + " devices the scratch table tracks");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(nullptr, DEBLUR_E_HIP,
+                        std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return DEBLUR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int deblur_debug_fft_noalloc(int32_t n, int32_t batch, int32_t which, const float* in, float* out, void* stream) {
+    if (n != 160 && n != 320 && n != 640) return fail(nullptr, DEBLUR_E_ARG, "n must be 160, 320 or 640");
+    if (batch < 1 || !in || !out || which < 0 || which > 3) return fail(nullptr, DEBLUR_E_ARG, "bad argument");
+    if (batch > kNoAllocMaxBatch)
+        return fail(nullptr, DEBLUR_E_ARG, "batch " + std::to_string(batch) + " exceeds the allocation-free limit of " +
+                                               std::to_string(kNoAllocMaxBatch) + " frames");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(nullptr, DEBLUR_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (s) {
+        hipDevice_t sdev = -1;
+        e = hipStreamGetDevice(s, &sdev);
+        if (e != hipSuccess)
+            return fail(nullptr, DEBLUR_E_HIP, std::string("hipStreamGetDevice: ") + hipGetErrorString(e));
+        if (sdev != dev)
+            return fail(nullptr, DEBLUR_E_ARG, "the stream belongs to device " + std::to_string(sdev) + ", device " +
+                                                   std::to_string(dev) + " is current");
+    }
+    unsigned char* base = nullptr;
+    int rc = scratch_address(dev, &base);
+    if (rc) return rc;
+    // The same launches as deblur_debug_fft, with the tables in scratch.
+    deblur_ctx tmp;
+    tmp.N = n;
+    tmp.nt = batch;
+    tmp.plan = deblur_plan{n, waves_hi(n), waves_hi(n), DEBLUR_ORDER_COLUMN_MAJOR, 1, 0.f};
+    tmp.tw = reinterpret_cast<float2*>(base);
+    tmp.tiles = reinterpret_cast<TileInfo*>(base + kNoAllocTwBytes);
+    tmp.tentX = reinterpret_cast<float*>(base + kNoAllocTwBytes + kNoAllocTileBytes);
+    const int n_tent = dbl::kMaxK * n;
+    const int fill = std::max(batch, n_tent);
+    hipLaunchKernelGGL(dbl::k_fill_fft_tables, dim3((fill + 255) / 256), dim3(256), 0, s, tmp.tiles, batch, n,
+                       tmp.tentX, n_tent);
+    switch (n) {
+        case 160: hipLaunchKernelGGL(dbl::k_make_twiddles<160>, dim3(1), dim3(256), 0, s, tmp.tw); break;
+        case 320: hipLaunchKernelGGL(dbl::k_make_twiddles<320>, dim3(1), dim3(256), 0, s, tmp.tw); break;
+        default: hipLaunchKernelGGL(dbl::k_make_twiddles<640>, dim3(1), dim3(256), 0, s, tmp.tw); break;
+    }
+    if (which == 0) {
+        row_fwd(&tmp, s, in, reinterpret_cast<float2*>(out), 0);
+    } else if (which == 3) {
+        row_inv(&tmp, s, reinterpret_cast<const float2*>(in), out, 0);
+    } else {
+        DISPATCH_NW(&tmp, tmp.plan.col_waves, launch_col_fft_dbg, s, reinterpret_cast<const float2*>(in),
+                    reinterpret_cast<float2*>(out), which == 1 ? -1 : 1);
+    }
+    e = hipGetLastError();
     if (e != hipSuccess) return fail(nullptr, DEBLUR_E_HIP, hipGetErrorString(e));
     return DEBLUR_OK;
 }

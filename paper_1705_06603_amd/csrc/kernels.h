@@ -248,6 +248,20 @@ __global__ void k_make_twiddles(float2* __restrict__ twg) {
     }
 }
 
+// Tables the stand-alone FFT stages read: every one of the batch's tiles is
+// a full n x n frame with one unmasked term (tent 1 everywhere).
+__global__ void k_fill_fft_tables(TileInfo* __restrict__ tiles, int batch, int n, float* __restrict__ tent,
+                                  int n_tent) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < batch) {
+        TileInfo t{};
+        t.sy = t.sx = t.by = t.bx = n;
+        t.nky = t.nkx = 1;
+        tiles[i] = t;
+    }
+    if (i < n_tent) tent[i] = 1.0f;
+}
+
 // x (frames) -> packed row half-spectra of b_k . x for each mask k of the
 // tile (masked != 0) or of x itself (masked == 0, one output).
 template <int N, int WV>
