@@ -1,11 +1,18 @@
 """Benchmark of the batched tile solve on one MI355X.
 
-One step = one full solve of the batched workload: 2048 x 2048 observed
-image in 8 x 8 tiles (32-px overlap, uneven edge tiles), 8 x 8 grid of 31 x 31
-Moffat PSFs, Poisson + read noise, smoothed TV, positivity, 200 Local-Solver
-iterations (20 D-R rounds of 10), i.e. init -> 20 graph-captured rounds ->
-output assembly.  Inputs (observation, weights, PSF spectra) are resident in
-HBM before the timed region starts.
+Default workload (the largest single-GPU configuration): 16384 x 16384
+observed image in 32 x 32 tiles (64-px overlap), 32 x 32 grid of 63 x 63
+Moffat PSFs, Poisson + read noise, smoothed TV, positivity.  One step = one
+warm-started solve: the CNN warm start on all 1024 tiles (one launch per
+layer) with the per-tile fallback judge, 20 graph-captured D-R rounds of 10
+Local-Solver steps (200 iterations), output assembly.  Inputs (observation,
+weights, PSF spectra, network weights) are resident in HBM before the timed
+region starts.  `--workload batched|large` times the other configurations
+(plain start) the same way.
+
+The convergence section (time to residual 1e-4, warm start vs plain start)
+runs on the 2048 x 2048 batched workload, where the warm-start network is
+trained on converged plain-solver pairs of fresh scenes.
 
 Prints one JSON line (see the keys below).  --gpus N > 1 is rejected: the
 solver runs every tile of the image on one GPU.
@@ -49,14 +56,19 @@ def kernel_source_hash():
 WORKLOAD_TEXT = {
     "batched": "batched: 2048x2048 image, 8x8 tiles (32-px overlap, uneven edge tiles), 8x8 grid of 31x31 "
                "Moffat PSFs, Poisson+read noise, smoothed TV + positivity, 200 iterations (20 D-R rounds x 10 "
-               "Local-Solver steps), one solve per step",
+               "Local-Solver steps), plain start, one solve per step",
     "large": "large: 8192x8192 image, 16x16 tiles of 512-576 px (64-px overlap), 16x16 grid of 63x63 Moffat "
              "PSFs with field-dependent FWHM and rotation, Poisson+read noise, smoothed TV + positivity, 300 "
-             "iterations (30 D-R rounds x 10 Local-Solver steps), one solve per step",
-    "combined": "combined: 16384x16384 image, 32x32 tiles (64-px overlap), 32x32 grid of 63x63 Moffat PSFs, "
-                "Poisson+read noise, smoothed TV + positivity, 300 iterations (30 D-R rounds x 10 "
-                "Local-Solver steps), one solve per step",
+             "iterations (30 D-R rounds x 10 Local-Solver steps), plain start, one solve per step",
+    "combined": "combined: 16384x16384 image, 32x32 tiles of 512 px + 64-px overlap, 32x32 grid of 63x63 Moffat "
+                "PSFs, Poisson+read noise, smoothed TV + positivity; CNN warm start on all 1024 tiles (one "
+                "launch per layer) with per-tile fallback, then 200 iterations (20 D-R rounds x 10 "
+                "Local-Solver steps), one warm-started solve per step",
 }
+
+# Workloads whose timed step starts from the network (the others from the
+# plain observed start).
+WARM_WORKLOADS = ("combined",)
 
 
 def parse_plan(text):
@@ -72,7 +84,7 @@ def parse_plan(text):
     return pl
 
 
-def build_workload(name="batched", tune=True, plan=None):
+def build_workload(name="batched", tune=True, plan=None, tune_reps=None):
     """Scene, PSFs and the noisy observation of a workload, on a context whose
     launch plan comes from the library's autotuner (or is given).
 
@@ -88,7 +100,10 @@ def build_workload(name="batched", tune=True, plan=None):
                             lam=w.lam, reg_param=w.eps, gamma=w.gamma, rho=w.rho)
     trials = []
     if plan is None and tune:
-        plan, trials = dl.autotune(params, psfs, n_inner=w.n_inner, reps=5)
+        # timed rounds per plan: fewer on the large images, where one round
+        # already spans tens of milliseconds
+        reps = tune_reps if tune_reps else (5 if w.M <= 2048 else 1)
+        plan, trials = dl.autotune(params, psfs, n_inner=w.n_inner, reps=reps)
     if plan is not None:
         params.fft_size = plan.frame
     ctx = dl.Context(params, psfs)
@@ -148,6 +163,17 @@ def tile_bytes(ctx):
     return out
 
 
+def step_floor_bytes(ctx):
+    """The method's algorithmic HBM floor of one inner iteration (one
+    Local-Solver step on every tile): per support pixel, x, u, y and W read
+    and x written (20 B), plus 8 B of PSF spectrum per term for H and for
+    H^T (8 K_t B), summed over the tiles."""
+    total = 0
+    for d in ctx.tiles:
+        total += (20 + 8 * d.n_terms_y * d.n_terms_x) * d.support_h * d.support_w
+    return total
+
+
 def kernel_variant(ctx, kernel):
     """Launch shape of one kernel family under the context's plan."""
     pl = ctx.plan()
@@ -182,22 +208,28 @@ def measured_traffic(ctx, workload, kernel):
 
 def _oracle_tile_steps(job):
     """Worker of cpu_baseline: one Local-Solver step of the FP64 oracle on each
-    of the given tiles in turn until the time budget is spent."""
+    of the given tiles in turn until the time budget is spent.  The
+    observation, weights and PSFs come from .npy files, memory-mapped, so a
+    worker reads only its tiles' blocks."""
+    from oracle import operator as op
     from oracle import solver
     from oracle.layout import make_layout
     from oracle.solver import Problem
     from threadpoolctl import threadpool_limits
-    geom, prior, y, W, psfs, tiles, budget_s = job
+    geom, prior, paths, backend, frame, tiles, budget_s = job
     threadpool_limits(1)          # one thread per worker process
+    y, W, psfs = (np.load(p, mmap_mode="r") for p in paths)
+    psfs = np.asarray(psfs, dtype=np.float64)
     L = make_layout(*geom)
-    prob = Problem(L, psfs, y, W, **prior)
-    x0 = solver.initial_tiles(prob, "observed")
+    operator = op.FFTOperator(L, psfs, frame) if backend == "fft" else None
+    prob = Problem(L, psfs, y, W, operator=operator, **prior)
     el, steps = 0.0, 0
     t_start = time.perf_counter()
     for t in itertools.cycle(tiles):   # the worker's tiles, again until the budget is spent
-        tau = solver.step_size(prob, t)          # setup, not timed
+        x0 = solver.initial_tiles(prob, "observed", tiles=[t])[0]   # setup, not timed
+        tau = solver.step_size(prob, t)                              # setup, not timed
         ts = time.perf_counter()
-        solver.local_solve(prob, t, x0[t], x0[t], 1, tau)
+        solver.local_solve(prob, t, x0, x0, 1, tau)
         el += time.perf_counter() - ts
         steps += 1
         if time.perf_counter() - t_start > budget_s:
@@ -211,6 +243,17 @@ def baseline_procs():
     return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def start_baseline_pool(procs):
     """Fork the CPU baseline's workers.  Called before anything touches the
     GPU, so the children are plain copies of a host-only process; they sit idle
@@ -220,26 +263,53 @@ def start_baseline_pool(procs):
 
 
 def cpu_baseline(pool, procs, psfs, y, W, w, budget_s=20.0):
-    """The FP64 oracle (direct convolution) on a bounded sample of the same
-    workload, on the host's cores: `procs` worker processes of one thread
-    each, every one doing Local-Solver steps on its share of seeded sampled
-    tiles for about budget_s seconds; the whole-image rate is the sum of the
-    workers' rates, extrapolated by tile count."""
+    """The FP64 oracle on a bounded sample of the same workload, on the
+    host's cores.  First one worker alone (the one-process rate), then
+    `procs` worker processes of one thread each, every one doing Local-Solver
+    steps on its share of seeded sampled tiles for about budget_s seconds;
+    the whole-image rate is the sum of the workers' rates, extrapolated by
+    tile count.  The oracle's operator is direct convolution; for the 63 x 63
+    PSFs its FP64 FFT backend (pinned equal to direct convolution) is used,
+    as one direct-convolution tile step there takes about a minute."""
+    import shutil
+    import tempfile
+
+    import scipy.fft
     from oracle.layout import make_layout
 
     geom = (w.M, w.tiles, w.pitch, w.overlap, w.psf_size, w.grid)
     L = make_layout(*geom)
+    backend = "direct" if w.psf_size <= 31 else "fft"
+    frame = scipy.fft.next_fast_len(max(max(L.support_shape(t)) for t in range(L.n_tiles)), real=True)
     order = np.random.default_rng(12345).permutation(L.n_tiles)
     prior = dict(lam=w.lam, reg_param=w.eps, gamma=w.gamma, rho=w.rho)
-    jobs = [(geom, prior, y, W, psfs, [int(t) for t in order[k::procs]], budget_s) for k in range(procs)]
-    out = pool.map(_oracle_tile_steps, jobs, chunksize=1)
+    tmp = tempfile.mkdtemp(prefix="deblur_baseline_")
+    try:
+        paths = []
+        for name, a in (("y", y), ("W", W), ("psfs", psfs)):
+            paths.append(os.path.join(tmp, name + ".npy"))
+            np.save(paths[-1], np.asarray(a, dtype=np.float32 if name != "psfs" else np.float64))
+        one = pool.apply(_oracle_tile_steps, ((geom, prior, paths, backend, frame,
+                                               [int(t) for t in order[:8]], budget_s / 2),))
+        jobs = [(geom, prior, paths, backend, frame, [int(t) for t in order[k::procs]], budget_s)
+                for k in range(procs)]
+        out = pool.map(_oracle_tile_steps, jobs, chunksize=1)
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
     steps = sum(n for n, _ in out)
     tile_steps_per_s = sum(n / el for n, el in out if n)
-    rate = (w.M * w.M) * tile_steps_per_s / L.n_tiles / 1e6
+    per_tile = (w.M * w.M) / L.n_tiles / 1e6
+    rate = tile_steps_per_s * per_tile
+    rate_one = (one[0] / one[1]) * per_tile if one[0] else None
+    kind = ("fp64 direct-convolution oracle" if backend == "direct" else
+            f"fp64 oracle with its FFT backend ({frame}x{frame} frames; the direct-convolution form is pinned "
+            f"equal to it and takes about a minute per tile step at 63x63 PSFs)")
     return {"value": rate, "unit": UNIT, "cores": procs, "kind": "oracle",
-            "sample": f"1 Local-Solver step (H + H^T + TV gradient + projected update) of the fp64 "
-                      f"direct-convolution oracle, {steps} tile-steps over {L.n_tiles} seeded-shuffled tiles, in {procs} "
-                      f"single-threaded processes for ~{budget_s:.0f} s each; whole-image rate = sum of the "
+            "one_process_value": rate_one, "cpu_model": cpu_model(),
+            "sample": f"1 Local-Solver step (H + H^T + TV gradient + projected update) of the {kind}, "
+                      f"{steps} tile-steps over {L.n_tiles} seeded-shuffled tiles of the same workload, in "
+                      f"{procs} single-threaded processes for ~{budget_s:.0f} s each (after one process alone "
+                      f"for ~{budget_s / 2:.0f} s: {one[0]} tile-steps); whole-image rate = sum of the "
                       f"processes' tile-step rates x (image pixels / tiles)"}
 
 
@@ -262,41 +332,123 @@ def schedule_iterations(w, rounds, growth):
     return sum(w.n_inner + growth * k for k in range(rounds))
 
 
-def convergence(ctx, w, args, fctx=None):
-    """Time and iterations to a D-R residual of 1e-4 from the plain start and
-    from the network's warm start (with per-tile fallback), same GPU, same
-    scene.  The network is trained first (untimed) on plain-solver pairs of
-    fresh scenes (seeds 10000+), held out from the benchmark scene; the warm
-    start then runs it on all tiles of the image in one launch per layer."""
+def train_network(w, args, scenes, tol, max_rounds, crops_per_tile, label):
+    """A warm-start network trained (untimed) on plain-solver pairs of fresh
+    scenes (seeds 10000+) of workload w: inputs are the warm-start inputs of a
+    tile, targets its plain solution at residual tol."""
     import torch
     from paper_1705_06603_amd import _lib as dl
     from paper_1705_06603_amd import train as tr
-    N = ctx.tiles[0].frame
-    scenes = args.train_scenes if args.train_scenes else (8 if ctx.n_tiles <= 64 else 2)
     t0 = time.perf_counter()
     tctx, _ = tr.workload_context(w)
     ins, outs = tr.make_pairs(tctx, w, seeds=range(10000, 10000 + scenes), crop=256,
-                              crops_per_tile=1, n_outer=w.n_outer)
+                              crops_per_tile=crops_per_tile, tol=tol, max_rounds=max_rounds)
     tctx.close()
     n_pairs = int(ins.shape[0])
     trainer = dl.Net(16, 256, 256, seed=3)
     losses = tr.train(trainer, ins, outs, steps=args.train_steps, batch=16, lr=2e-3)
     torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
     del ins, outs
-    # inference network sized for every tile of the image at once
+    info = {"workload": w.name, "pairs": n_pairs, "scenes": scenes, "crop": 256,
+            "target": f"plain solve to residual {tol:g} (at most {max_rounds} rounds)",
+            "steps": args.train_steps, "batch": 16, "loss_first": losses[0], "loss_last": losses[-1],
+            "seconds": round(time.perf_counter() - t0, 2)}
+    print(f"# {label}: network trained on {n_pairs} pairs in {info['seconds']} s", file=sys.stderr, flush=True)
+    return trainer, info
+
+
+def warm_network(ctx, w, args):
+    """The network of the warm-started workload: trained on a 4096 x 4096
+    image of the same PSF model and tiling (8 x 8 tiles of 512 px + 64,
+    8 x 8 Moffat grid of 63 x 63), then copied into an inference network
+    sized for every tile of the image at once."""
+    import dataclasses
+    from paper_1705_06603_amd import _lib as dl
+    tw = dataclasses.replace(w, name=w.name + "-train", M=4096, tiles=8, grid=8)
+    trainer, info = train_network(tw, args, scenes=args.train_scenes or 4, tol=1e-3, max_rounds=600,
+                                  crops_per_tile=4, label="warm start")
+    N = ctx.tiles[0].frame
     net = dl.Net(ctx.n_tiles, N, N, params=trainer.get_params(), inference_only=True)
     trainer.close()
-    out = {"tol": 1e-4, "n_inner": w.n_inner, "gamma": w.gamma,
-           "training": {"pairs": n_pairs, "scenes": scenes, "crop": 256,
-                        "steps": args.train_steps, "batch": 16, "loss_first": losses[0], "loss_last": losses[-1],
-                        "seconds": round(train_s, 2)}}
+    return net, info
+
+
+def network_cost(ctx, net):
+    """Forward time of the network on every tile of ctx at once and the MFMA
+    utilisation of a 32 -> 32 layer."""
+    N = ctx.tiles[0].frame
+    frames, _ = ctx.warm_inputs()
+    B = ctx.n_tiles
+    ms_all, ms_mid = net.time_forward(frames, reps=5)
+    flop_mid = 2.0 * 9 * 32 * 32 * B * N * N
+    # the 32 -> 32 layer reads and writes one bf16 activation map of 32
+    # channels: 144 flop per byte, below the bf16 MFMA / HBM balance of
+    # 2500 / 8 = 312, so its roofline is the HBM one
+    bytes_mid = 2.0 * 32 * 2 * B * N * N
+    return {"forward_ms_per_batch": round(ms_all, 3), "batch_tiles": B, "frame": N,
+            "mid_layer_ms": round(ms_mid, 4), "mid_layer_TFLOPs": round(flop_mid / (ms_mid * 1e-3) / 1e12, 1),
+            "mfma_bf16_peak_TFLOPs": 2500.0,
+            "mfma_utilisation": round(flop_mid / (ms_mid * 1e-3) / 2.5e15, 4),
+            "mid_layer_algorithmic_bytes": bytes_mid,
+            "mid_layer_GBps": round(bytes_mid / (ms_mid * 1e-3) / 1e9, 1),
+            "mid_layer_hbm_frac": round(bytes_mid / (ms_mid * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def timed_solves(ctx, w, steps, net=None):
+    """ms per solve of `steps` back-to-back solves (init or warm start,
+    n_outer graph-captured rounds, assembly) between HIP events on the
+    context stream."""
+    import torch
     stream = torch.cuda.current_stream()
-    # plain and warm start with the fixed schedule; plain start with the
-    # paper's growing schedule (n_inner + n_inner k steps in round k); plain
-    # start with the FISTA Local-Solver
-    labels = ("plain", "warm", "plain_growing") + (("plain_fista",) if fctx is not None else ())
-    for label in labels:
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    res = None
+    for _ in range(steps):
+        if net is not None:
+            ctx.init_cnn(net)
+        else:
+            ctx.init()
+        res = ctx.run(w.n_outer, w.n_inner)
+        ctx.assemble()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, res
+
+
+def convergence(args):
+    """On the batched workload (2048 x 2048): time and iterations to a D-R
+    residual of 1e-4 from the plain start, from the network's warm start
+    (with per-tile fallback), with the growing schedule and with the FISTA
+    Local-Solver; plus the FISTA solve throughput.  The network is trained
+    first (untimed) on converged plain-solver pairs (residual 1e-4) of fresh
+    scenes (seeds 10000+), held out from the benchmark scene (seed 2)."""
+    import torch
+    from paper_1705_06603_amd import _lib as dl
+    print("# convergence: batched workload", file=sys.stderr, flush=True)
+    ctx, w, scene, psfs, y, W, _ = build_workload("batched", tune=not args.no_autotune)
+    N = ctx.tiles[0].frame
+    trainer, info = train_network(w, args, scenes=args.train_scenes or 8, tol=1e-4, max_rounds=2000,
+                                  crops_per_tile=1, label="convergence")
+    net = dl.Net(ctx.n_tiles, N, N, params=trainer.get_params(), inference_only=True)
+    trainer.close()
+    out = {"workload": WORKLOAD_TEXT["batched"], "tol": 1e-4, "n_inner": w.n_inner, "gamma": w.gamma,
+           "plan": ctx.plan().as_dict(), "training": info}
+    fctx = fista_context(ctx, psfs, y, W)
+    iters = w.n_outer * w.n_inner
+    pms, _ = timed_solves(ctx, w, 1)
+    pms, _ = timed_solves(ctx, w, 20)
+    timed_solves(fctx, w, 1)
+    fms, _ = timed_solves(fctx, w, 20)
+    fk = fctx.time_kernels(reps=20)
+    out["fista_throughput"] = {"ms_per_solve": round(fms, 3),
+                               "value": round((w.M * w.M) * iters / (fms * 1e-3) / 1e6, 2),
+                               "plain_ms_per_solve": round(pms, 3),
+                               "plain_value": round((w.M * w.M) * iters / (pms * 1e-3) / 1e6, 2),
+                               "unit": UNIT, "row_update_ms": round(fk["row_update"], 5)}
+    stream = torch.cuda.current_stream()
+    for label in ("plain", "warm", "plain_growing", "plain_fista"):
         growth = w.n_inner if label == "plain_growing" else 0
         c = fctx if label == "plain_fista" else ctx
         torch.cuda.synchronize()
@@ -322,23 +474,10 @@ def convergence(ctx, w, args, fctx=None):
                       "iterations_to_1e-2": first(1e-2)}
         if label == "warm":
             out[label]["fallback_tiles"] = nf
-    # network inference cost (all tiles in one batch) and MFMA utilisation of a 32 -> 32 layer
-    frames, _ = ctx.warm_inputs()
-    B = ctx.n_tiles
-    ms_all, ms_mid = net.time_forward(frames, reps=10)
-    flop_mid = 2.0 * 9 * 32 * 32 * B * N * N
-    # the 32 -> 32 layer reads and writes one bf16 activation map of 32
-    # channels: 144 flop per byte, below the bf16 MFMA / HBM balance of
-    # 2500 / 8 = 312, so its roofline is the HBM one
-    bytes_mid = 2.0 * 32 * 2 * B * N * N
-    out["network"] = {"forward_ms_per_batch": round(ms_all, 3), "batch_tiles": B, "frame": N,
-                      "mid_layer_ms": round(ms_mid, 4), "mid_layer_TFLOPs": round(flop_mid / (ms_mid * 1e-3) / 1e12, 1),
-                      "mfma_bf16_peak_TFLOPs": 2500.0,
-                      "mfma_utilisation": round(flop_mid / (ms_mid * 1e-3) / 2.5e15, 4),
-                      "mid_layer_algorithmic_bytes": bytes_mid,
-                      "mid_layer_GBps": round(bytes_mid / (ms_mid * 1e-3) / 1e9, 1),
-                      "mid_layer_hbm_frac": round(bytes_mid / (ms_mid * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    out["network"] = network_cost(ctx, net)
     net.close()
+    fctx.close()
+    ctx.close()
     return out
 
 
@@ -348,16 +487,18 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-budget", type=float, default=16.0)
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the context's default launch plan")
     ap.add_argument("--plan", default=None, help="fixed launch plan 'frame,col_waves,row_waves,order[,groups]' "
-                                                 "(order: column_major | tile_major | heavy_first; groups 1 or 2)")
-    ap.add_argument("--workload", default="batched", choices=sorted(WORKLOAD_TEXT),
-                    help="batched is the headline configuration; the others are reported the same way")
+                                                 "(order: column_major | tile_major | heavy_first; groups 1, 2 or 4)")
+    ap.add_argument("--workload", default="combined", choices=sorted(WORKLOAD_TEXT),
+                    help="combined (16384^2, warm-started) is the headline configuration; the others are "
+                         "reported the same way from the plain start")
+    ap.add_argument("--plain-start", action="store_true", help="time the combined workload from the plain start")
     ap.add_argument("--max-rounds", type=int, default=1500)
     ap.add_argument("--train-scenes", type=int, default=0,
-                    help="training scenes (0: 8 for up to 64 tiles, else 2)")
+                    help="training scenes (0: 8 for the convergence network, 4 for the warm-start network)")
     ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (for HBM counter calibration)")
@@ -365,7 +506,7 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs all tiles on one GPU; --gpus must be 1"}))
         sys.exit(2)
-    want_baseline = not (args.no_cpu_baseline or args.copy_calibration) and args.workload == "batched"
+    want_baseline = not (args.no_cpu_baseline or args.copy_calibration)
     procs = baseline_procs()
     pool = start_baseline_pool(procs) if want_baseline else None
 
@@ -380,14 +521,22 @@ def main():
         print(json.dumps({"copy_bytes_per_direction": a.numel() * 4}))
         return
 
-    print("# building workload", file=sys.stderr, flush=True)
+    print(f"# building workload {args.workload}", file=sys.stderr, flush=True)
     ctx, w, scene, psfs, y, W, trials = build_workload(args.workload, tune=not args.no_autotune,
                                                        plan=parse_plan(args.plan) if args.plan else None)
+    del scene
     n_outer, n_inner = w.n_outer, w.n_inner
+    warm = args.workload in WARM_WORKLOADS and not args.plain_start
+    net, net_info = warm_network(ctx, w, args) if warm else (None, None)
     stream = torch.cuda.current_stream()
+    nf_last = []
 
     def step():
-        ctx.init()
+        if warm:
+            _, nf = ctx.init_cnn(net)
+            nf_last[:] = [nf]
+        else:
+            ctx.init()
         res = ctx.run(n_outer, n_inner)
         ctx.assemble()
         return res
@@ -398,7 +547,7 @@ def main():
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    print("# timed", file=sys.stderr, flush=True)
+    print(f"# timed: {args.steps} steps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     e0.record(stream)
     res = None
@@ -411,26 +560,40 @@ def main():
     ms_per_step = ms_total / args.steps
     iters = n_outer * n_inner
     value = (w.M * w.M) * iters * args.steps / (ms_total * 1e-3) / 1e6
+    print(f"# timed: {ms_per_step:.2f} ms per step, {value:.1f} {UNIT}", file=sys.stderr, flush=True)
 
-    # Per-kernel launch durations (HIP events on the context stream).
-    kms = ctx.time_kernels(reps=20)
+    # Per-kernel launch durations (HIP events on the context stream, every
+    # launch covering all tiles) and the HBM roofline of the inner iteration:
+    # the method's algorithmic floor per iteration over the four frame
+    # kernels' summed launch time.
+    kms = ctx.time_kernels(reps=20 if w.M <= 2048 else 5)
     kb = tile_bytes(ctx)
-    per_step_ms = {k: kms[k] * iters for k in KERNELS_PER_STEP}
-    dom = max(per_step_ms, key=per_step_ms.get)
-    achieved = kb[dom] / (kms[dom] * 1e-3) / 1e9
-    traffic = measured_traffic(ctx, args.workload, dom)
+    step_ms = sum(kms[k] for k in KERNELS_PER_STEP)
+    floor = step_floor_bytes(ctx)
+    achieved = floor / (step_ms * 1e-3) / 1e9
+    counters = [measured_traffic(ctx, args.workload, k) for k in KERNELS_PER_STEP]
+    traffic = sum(counters) if all(c is not None for c in counters) else None
+    dom = max(KERNELS_PER_STEP, key=lambda k: kms[k])
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dom, "kernel_ms": round(kms[dom], 5),
-                "algorithmic_bytes_per_launch": kb[dom],
+                "kernel": "inner iteration: " + " + ".join(KERNELS_PER_STEP),
+                "kernel_ms": round(step_ms, 5), "algorithmic_bytes_per_launch": floor,
+                "algorithmic_bytes_rule": "sum over tiles of (20 + 8 K_t) B per support pixel",
+                "frac_from_ms_per_step": round(floor * iters / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "dominant_kernel": {"name": dom, "ms": round(kms[dom], 5), "design_bytes": kb[dom],
+                                    "design_GBps": round(kb[dom] / (kms[dom] * 1e-3) / 1e9, 1),
+                                    "design_frac": round(kb[dom] / (kms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                    "traffic": counters[KERNELS_PER_STEP.index(dom)]},
                 "all_kernels_ms": {k: round(v, 5) for k, v in kms.items()},
-                "all_kernels_GBps": {k: round(kb[k] / (kms[k] * 1e-3) / 1e9, 1) for k in kms}}
+                "all_kernels_design_GBps": {k: round(kb[k] / (kms[k] * 1e-3) / 1e9, 1) for k in kms}}
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": WORKLOAD_TEXT[args.workload],
+        "config": {"workload": WORKLOAD_TEXT[args.workload] if warm or args.workload != "combined"
+                   else WORKLOAD_TEXT[args.workload].replace("CNN warm start on all 1024 tiles (one launch per "
+                                                             "layer) with per-tile fallback, then ", "plain start, "),
                    "global_pixels": w.M * w.M, "iterations": iters, "tiles": ctx.n_tiles,
                    "fft_frame": ctx.tiles[0].frame, "parallelism": "single GPU, all tiles batched",
                    "plan": ctx.plan().as_dict()},
@@ -438,46 +601,25 @@ def main():
         "wall_s": round(wall, 3),
         "roofline": roofline,
     }
+    if warm:
+        out["warm_start"] = {"fallback_tiles": nf_last[0] if nf_last else None, "training": net_info,
+                             "network": network_cost(ctx, net)}
+        net.close()
     if trials:
         dflt = trials[0]   # the tuner measures a new context's own plan first
         best = min(trials, key=lambda t: t.us_per_iter)
         out["autotune"] = {"plans_measured": len(trials), "frames": sorted({t.frame for t in trials}),
                            "best": best.as_dict(), "default": dflt.as_dict(),
                            "worst_us_per_iter": round(max(t.us_per_iter for t in trials), 2)}
+    ctx.close()
+    torch.cuda.empty_cache()
     if not args.no_convergence:
-        # the FISTA Local-Solver on the same workload and plan: its step
-        # throughput (same timed solve as above) and, below, its time to 1e-4
-        print("# FISTA Local-Solver", file=sys.stderr, flush=True)
-        fctx = fista_context(ctx, psfs, y, W)
-
-        def fstep():
-            fctx.init()
-            fctx.run(n_outer, n_inner)
-            fctx.assemble()
-
-        fstep()
-        torch.cuda.synchronize()
-        f0 = torch.cuda.Event(enable_timing=True)
-        f1 = torch.cuda.Event(enable_timing=True)
-        f0.record(stream)
-        for _ in range(args.steps):
-            fstep()
-        f1.record(stream)
-        torch.cuda.synchronize()
-        fms = f0.elapsed_time(f1) / args.steps
-        fk = fctx.time_kernels(reps=20)
-        out["fista"] = {"ms_per_step": round(fms, 3),
-                        "value": round((w.M * w.M) * iters / (fms * 1e-3) / 1e6, 2), "unit": UNIT,
-                        "row_update_ms": round(fk["row_update"], 5)}
-        print("# convergence: plain vs warm start vs FISTA", file=sys.stderr, flush=True)
-        out["convergence"] = convergence(ctx, w, args, fctx)
-        fctx.close()
+        out["convergence"] = convergence(args)
     if pool is not None:
         print(f"# cpu baseline ({procs} processes)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(pool, procs, psfs, y, W, w, args.cpu_budget)
         pool.close()
         pool.join()
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -159,15 +159,16 @@ def local_solve(problem, t, w0, u, n_inner, tau=None, method="pg"):
     return w
 
 
-def initial_tiles(problem, mode="observed"):
-    """x^0 per tile ('zero' or 'observed'); u^0 = x^0.
+def initial_tiles(problem, mode="observed", tiles=None):
+    """x^0 per tile ('zero' or 'observed'); u^0 = x^0.  ``tiles`` (default:
+    all) lists the tiles to return, in that order.
 
     'observed': max(y, 0) read at the nearest observed pixel (coordinates
     clamped into [0, M)), so all tiles start from one common image on X.
     """
     L = problem.layout
     out = []
-    for t in range(problem.n_tiles):
+    for t in (range(problem.n_tiles) if tiles is None else tiles):
         shape = L.support_shape(t)
         if mode == "zero":
             out.append(np.zeros(shape))

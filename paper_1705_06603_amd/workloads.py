@@ -86,7 +86,7 @@ WORKLOADS = {
     # 16384 x 16384, 32 x 32 tiles, 64-px overlap, 63 x 63 Moffat PSFs.
     "combined": Workload("combined", M=16384, tiles=32, pitch=512, overlap=64, grid=32,
                          psf_size=63, psf_kind="moffat", noise="poisson",
-                         n_iter=300, gamma=4.0, seed=5),
+                         n_iter=200, gamma=4.0, seed=5),
 }
 
 
