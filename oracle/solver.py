@@ -236,21 +236,26 @@ class Result:
 
 
 def solve(problem, n_outer, n_inner=10, init="observed", x0=None, inner_growth=0,
-          consensus=True, callback=None, local_solver="pg"):
+          consensus=True, callback=None, local_solver="pg", tile_map=None):
     """Algorithm 1 with n_inner(k) = n_inner + inner_growth * k Local-Solver steps.
 
     ``consensus=False`` skips the consensus step (the paper's 'independent'
     baseline: each tile is deblurred on its own and the tiles are blended
     with omega at the end).  ``local_solver`` is "pg" or "fista"; a FISTA
-    run restarts in every round.
+    run restarts in every round.  ``tile_map`` (optional) runs the round's
+    independent local solves: it takes a list of argument tuples of
+    :func:`local_solve` after ``problem`` and returns their results in
+    order (the default calls local_solve on each in turn).
     """
+    if tile_map is None:
+        tile_map = lambda jobs: [local_solve(problem, *j) for j in jobs]   # noqa: E731
     x = [a.copy() for a in (x0 if x0 is not None else initial_tiles(problem, init))]
     u = [a.copy() for a in x]
     taus = [step_size(problem, t) for t in range(problem.n_tiles)]
     res = []
     for k in range(n_outer):
         n_k = n_inner + inner_growth * k
-        x = [local_solve(problem, t, x[t], u[t], n_k, taus[t], local_solver) for t in range(problem.n_tiles)]
+        x = list(tile_map([(t, x[t], u[t], n_k, taus[t], local_solver) for t in range(problem.n_tiles)]))
         if consensus:
             u_new, _ = consensus_step(problem, x, u)
         else:

@@ -75,15 +75,23 @@ def tile_inputs(problem):
     return ins, scales
 
 
-def network_start(problem, net_params, bf16=True):
+def network_start_tile(problem, net_params, t, bf16=True):
+    """x0_t = max(0, s_t * net(yhat_t)) of one tile."""
+    s = tile_scale(problem, t)
+    o, _ = cnn.forward(net_params, (_nearest_observed(problem, t) / s)[None], bf16=bf16)
+    return np.maximum(s * o[0], 0.0)
+
+
+def network_start(problem, net_params, bf16=True, tile_map=None):
     """x0_t = max(0, s_t * net(yhat_t)) per tile.  net_params: list of (W, b)
-    of ``oracle.cnn``; bf16 rounds where the GPU network stores BF16."""
-    ins, scales = tile_inputs(problem)
-    out = []
-    for t in range(problem.n_tiles):
-        o, _ = cnn.forward(net_params, ins[t][None], bf16=bf16)
-        out.append(np.maximum(scales[t] * o[0], 0.0))
-    return out
+    of ``oracle.cnn``; bf16 rounds where the GPU network stores BF16.
+    ``tile_map`` (optional) evaluates the tiles: it takes a list of argument
+    tuples (net_params, t, bf16) of :func:`network_start_tile` after
+    ``problem`` and returns the results in order."""
+    jobs = [(net_params, t, bf16) for t in range(problem.n_tiles)]
+    if tile_map is None:
+        return [network_start_tile(problem, *j) for j in jobs]
+    return list(tile_map(jobs))
 
 
 def gradient_map(problem, t, x, tau):
@@ -115,9 +123,9 @@ def judge(problem, x_net, x_plain, taus=None, margin=MARGIN):
     return starts, keep, maps
 
 
-def warm_start(problem, net_params, bf16=True, taus=None, margin=MARGIN):
+def warm_start(problem, net_params, bf16=True, taus=None, margin=MARGIN, tile_map=None):
     """The whole warm start: network starts, plain starts, per-tile judge.
     Returns (starts, keep, maps) as :func:`judge`."""
-    x_net = network_start(problem, net_params, bf16=bf16)
+    x_net = network_start(problem, net_params, bf16=bf16, tile_map=tile_map)
     x_plain = solver.initial_tiles(problem, "observed")
     return judge(problem, x_net, x_plain, taus, margin)
