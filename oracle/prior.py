@@ -79,3 +79,32 @@ def lipschitz(kind, param):
     if kind == "huber":
         return 8.0
     raise ValueError(kind)
+
+
+def value_change(x, dx, kind, param, bc="neumann"):
+    """phi(D (x + dx)) - phi(D x), summed per pixel in a form without
+    cancellation: with a = D x and b = D (x + dx) = a + D dx,
+    |b|^2 - |a|^2 = <D dx, a + b>, and
+      smoothed TV: sqrt(|b|^2 + eps^2) - sqrt(|a|^2 + eps^2)
+                   = (|b|^2 - |a|^2) / (sqrt(|b|^2 + eps^2) + sqrt(|a|^2 + eps^2));
+      Huber: (|b|^2 - |a|^2) / 2 where both norms are <= delta,
+             delta (|b|^2 - |a|^2) / (|b| + |a|) where both exceed it,
+             the plain difference of the two pieces otherwise."""
+    ah, av = forward_diff(x, bc)
+    dh, dv = forward_diff(dx, bc)
+    bh, bv = ah + dh, av + dv
+    na2, nb2 = ah * ah + av * av, bh * bh + bv * bv
+    diff = dh * (ah + bh) + dv * (av + bv)
+    if kind == "tv":
+        return float(np.sum(diff / (np.sqrt(nb2 + param * param) + np.sqrt(na2 + param * param))))
+    if kind == "huber":
+        na, nb = np.sqrt(na2), np.sqrt(nb2)
+        ha = np.where(na <= param, 0.5 * na2, param * (na - 0.5 * param))
+        hb = np.where(nb <= param, 0.5 * nb2, param * (nb - 0.5 * param))
+        both_in = (na <= param) & (nb <= param)
+        both_out = (na > param) & (nb > param)
+        out = np.where(both_in, 0.5 * diff, hb - ha)
+        out = np.where(both_out, param * diff / np.where(both_out, na + nb, 1.0), out)
+        return float(np.sum(out))
+    raise ValueError(kind)
+

@@ -36,7 +36,33 @@ restarted at every call from y_1 = w_0 = the warm start.  The run returns
 w_n, so the last step's momentum (which would only move the unused y_{n+1})
 is taken as 0.
 
-One "iteration" is one projected-gradient step on every tile; consensus runs
+The paper's own Local-Solver (Section IV-B) is VMLM-B, a limited-memory
+variable-metric (BFGS) method with bound constraints whose step length comes
+from a line search (method "vmlmb").  Each iteration, from w with gradient g:
+
+    F    = the free variables: all but those with w_i <= 0 and g_i > 0
+           (every variable without positivity)
+    d    = -F . B (F . g)         B the limited-memory inverse BFGS matrix of
+                                  the last m pairs (s_i, y_i) (two-loop
+                                  recursion, initial scaling <s, y>/<y, y> of
+                                  the newest pair, 1 with no pair)
+    w(a) = P(w + a d),  a = tau_t with no pair, else 1, halved until
+           f(w(a)) - f(w) <= c1 <g, w(a) - w>           (c1 = 1e-4, Armijo)
+    s    = w(a) - w,  y = g(w(a)) - g,  kept if <s, y> > 0 (else the memory
+           is cleared), the oldest pair dropped beyond m = 5.
+
+The change f(w(a)) - f(w) of the prox objective is evaluated through its
+exact expansion in D = w(a) - w (prox_objective_change), which has no
+cancellation: a difference of two objective values would stop the line
+search once the decrease falls below the rounding of the values themselves.
+B is positive definite (every kept pair has <s, y> > 0), so d is a descent
+direction whenever F . g != 0; with no pair the step is the projected
+gradient step of length tau_t, which satisfies the Armijo test by the
+descent lemma.  If 30 halvings fail (rounding), the iteration takes no step
+and clears the memory.  The memory starts empty at every call (each round's
+Local-Solver run is a fresh VMLM-B run warm-started from x_t).
+
+One "iteration" is one Local-Solver step on every tile; consensus runs
 after every n_inner of them.  The residual is the D-R fixed-point residual
 ||u^{k+1} - u^k|| / ||u^{k+1}|| over all tiles.  The output image is
 sum_t omega_t x_t on X.
@@ -113,6 +139,22 @@ def prox_objective(problem, t, w, u):
     return data + reg + 0.5 * float(np.sum(problem.alpha_t(t) * e * e))
 
 
+def prox_objective_change(problem, t, w, u, dw, r=None):
+    """prox_objective(w + dw) - prox_objective(w) by its exact expansion:
+    with r = H_t w - y_t and e = H_t dw,
+      1/2 sum W (r + e)^2 - 1/2 sum W r^2 = sum W e (r + e/2),
+      1/2 sum alpha (w + dw - u)^2 - 1/2 sum alpha (w - u)^2
+          = sum alpha dw (w - u + dw/2),
+    and the regulariser's change per pixel (prior.value_change)."""
+    if r is None:
+        r = problem.H(t, w) - problem.y_t(t)
+    e = problem.H(t, dw)
+    data = float(np.sum(problem.W_t(t) * e * (r + 0.5 * e)))
+    reg = problem.lam * prior.value_change(w, dw, problem.reg, problem.reg_param, problem.bc)
+    metric = float(np.sum(problem.alpha_t(t) * dw * (w - u + 0.5 * dw)))
+    return data + reg + metric
+
+
 def prox_gradient(problem, t, w, u):
     """Gradient of the smooth part of the prox objective at w."""
     r = problem.W_t(t) * (problem.H(t, w) - problem.y_t(t))
@@ -134,10 +176,88 @@ def fista_momentum(n_inner):
     return beta
 
 
+VMLMB_MEMORY = 5
+ARMIJO_C1 = 1e-4
+MAX_BACKTRACKS = 30
+
+
+def free_mask(problem, w, g):
+    """1 on the free variables of the bound w >= 0, 0 on the active ones
+    (w_i <= 0 with g_i > 0, where the projected step stays on the bound)."""
+    if not problem.positivity:
+        return np.ones_like(w)
+    return np.where((w <= 0.0) & (g > 0.0), 0.0, 1.0)
+
+
+def lbfgs_apply(pairs, q):
+    """B q for the limited-memory inverse BFGS matrix B of `pairs` (oldest
+    first, each (s, y) with <s, y> > 0), by the two-loop recursion: the
+    newest pair first, then the initial matrix <s, y>/<y, y> I of the newest
+    pair (I with no pair), then the pairs oldest first."""
+    q = q.copy()
+    coef = []
+    for s, y in reversed(pairs):
+        a = float(np.sum(s * q)) / float(np.sum(s * y))
+        q -= a * y
+        coef.append(a)
+    if pairs:
+        s, y = pairs[-1]
+        q *= float(np.sum(s * y)) / float(np.sum(y * y))
+    for (s, y), a in zip(pairs, reversed(coef)):
+        b = float(np.sum(y * q)) / float(np.sum(s * y))
+        q += (a - b) * s
+    return q
+
+
+def vmlmb(problem, t, w0, u, n_iter, tau, memory=VMLMB_MEMORY, history=None):
+    """n_iter VMLM-B iterations on the prox subproblem of tile t from w0
+    (module docstring).  history, if a list, receives per iteration
+    (prox objective after it, accepted step length or 0, number of halvings,
+    number of pairs in memory after it)."""
+    w = w0.copy()
+    g = prox_gradient(problem, t, w, u)
+    f = prox_objective(problem, t, w, u)
+    pairs = []
+    for _ in range(n_iter):
+        F = free_mask(problem, w, g)
+        d = -F * lbfgs_apply(pairs, F * g)
+        a = tau if not pairs else 1.0
+        accepted, halvings = False, 0
+        r = problem.H(t, w) - problem.y_t(t)
+        for _ in range(MAX_BACKTRACKS):
+            wa = w + a * d
+            if problem.positivity:
+                wa = np.maximum(wa, 0.0)
+            df = prox_objective_change(problem, t, w, u, wa - w, r)
+            if df <= ARMIJO_C1 * float(np.sum(g * (wa - w))):
+                accepted = True
+                break
+            a *= 0.5
+            halvings += 1
+        if not accepted:
+            pairs = []
+            if history is not None:
+                history.append((f, 0.0, halvings, 0))
+            continue
+        ga = prox_gradient(problem, t, wa, u)
+        s, y = wa - w, ga - g
+        if float(np.sum(s * y)) > 0.0:
+            pairs = (pairs + [(s, y)])[-memory:]
+        else:
+            pairs = []
+        w, g, f = wa, ga, f + df
+        if history is not None:
+            history.append((f, a, halvings, len(pairs)))
+    return w
+
+
 def local_solve(problem, t, w0, u, n_inner, tau=None, method="pg"):
     """n_inner steps on the prox subproblem of tile t: projected gradient
-    ("pg") or its accelerated form ("fista", see the module docstring)."""
+    ("pg"), its accelerated form ("fista") or VMLM-B ("vmlmb"); see the
+    module docstring."""
     tau = step_size(problem, t) if tau is None else tau
+    if method == "vmlmb":
+        return vmlmb(problem, t, w0, u, n_inner, tau)
     if method == "pg":
         w = w0.copy()
         for _ in range(n_inner):
@@ -241,8 +361,9 @@ def solve(problem, n_outer, n_inner=10, init="observed", x0=None, inner_growth=0
 
     ``consensus=False`` skips the consensus step (the paper's 'independent'
     baseline: each tile is deblurred on its own and the tiles are blended
-    with omega at the end).  ``local_solver`` is "pg" or "fista"; a FISTA
-    run restarts in every round.  ``tile_map`` (optional) runs the round's
+    with omega at the end).  ``local_solver`` is "pg", "fista" or "vmlmb"; a FISTA
+    run restarts in every round, as does a "vmlmb" run (empty memory).
+    ``tile_map`` (optional) runs the round's
     independent local solves: it takes a list of argument tuples of
     :func:`local_solve` after ``problem`` and returns their results in
     order (the default calls local_solve on each in turn).
