@@ -84,9 +84,24 @@ enum {
  * (each D-R round, each deblur_solve_tiles call) from y_1 = the current x, and
  * ending on w_n (the last step's beta is 0).  It keeps one more frame per tile
  * and is not available with the growing schedule. */
+/* VMLM-B (Section IV-B: the paper's Local-Solver, a limited-memory
+ * variable-metric BFGS method with bound constraints whose step comes from
+ * a line search).  Per tile and iteration, from w with prox gradient g:
+ * free variables F = all but w_i <= 0 with g_i > 0; d = -F B (F g) with B the
+ * inverse BFGS matrix of the last 5 pairs (s, y) (two-loop recursion, initial
+ * scaling <s,y>/<y,y> of the newest pair); w(a) = P(w + a d) with a = tau_t
+ * when the memory is empty, else 1, halved until the prox objective's change
+ * (evaluated through its exact expansion in w(a) - w) is at most
+ * 1e-4 <g, w(a) - w>; the pair (w(a) - w, g(w(a)) - g) is kept if its inner
+ * product is positive, else the memory is cleared; after 30 trials the tile
+ * takes no step and clears its memory.  The memory starts empty at every run
+ * of n iterations (each D-R round, each deblur_solve_tiles call).  Every
+ * line-search trial ends with a 4-byte readback, so runs with this solver are
+ * launched eagerly (no HIP graph); it keeps 16 more frames per tile. */
 enum {
     DEBLUR_SOLVER_PG = 0,     /* projected gradient                              */
-    DEBLUR_SOLVER_FISTA = 1   /* accelerated projected gradient (FISTA)          */
+    DEBLUR_SOLVER_FISTA = 1,  /* accelerated projected gradient (FISTA)          */
+    DEBLUR_SOLVER_VMLMB = 2   /* limited-memory BFGS with bounds (VMLM-B)        */
 };
 
 enum {

@@ -18,7 +18,7 @@ MODEL_INTERP, MODEL_LOCAL = 0, 1
 REG_SMOOTH_TV, REG_HUBER = 0, 1
 BC_NEUMANN, BC_CIRCULAR = 0, 1
 INIT_ZERO, INIT_OBSERVED, INIT_GIVEN = 0, 1, 2
-SOLVER_PG, SOLVER_FISTA = 0, 1
+SOLVER_PG, SOLVER_FISTA, SOLVER_VMLMB = 0, 1, 2
 N_KERNELS = 5
 KERNEL_NAMES = ("col_H", "row_resid", "col_Ht", "row_update", "consensus")
 

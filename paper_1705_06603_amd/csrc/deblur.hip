@@ -16,6 +16,7 @@
 #include "../../include/deblur.h"
 #include "kernels.h"
 #include "cnn.h"
+#include "vmlmb.h"
 
 using dbl::Cover;
 using dbl::PackDesc;
@@ -180,6 +181,17 @@ struct deblur_ctx {
     int* use_cnn = nullptr;
     bool fista = false;           // Local-Solver: FISTA (else projected gradient)
     float* wbuf = nullptr;        // FISTA: the last projected-gradient point w_j per tile frame
+    bool vmlmb = false;           // Local-Solver: VMLM-B (limited-memory BFGS with bounds)
+    float* vm_g[2] = {nullptr, nullptr};   // VMLM-B: prox gradient frames (current, next)
+    float* vm_r[2] = {nullptr, nullptr};   // VMLM-B: unweighted residual H w - y frames
+    float* vm_d = nullptr;        // VMLM-B: direction (the two-loop's q and r)
+    float* vm_delta = nullptr;    // VMLM-B: trial step D
+    float* vm_S = nullptr;        // VMLM-B: kVmMem s frames (ring)
+    float* vm_Y = nullptr;        // VMLM-B: kVmMem y frames (ring)
+    dbl::VmTile* vm_tile = nullptr;
+    double* vm_part = nullptr;    // VMLM-B: per-block partial sums
+    int* vm_search = nullptr;     // VMLM-B: tiles still searching
+    int vm_gc = 0, vm_rc = 0;     // current gradient / residual buffer
     std::vector<void*> allocs;
     std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;   // (steps, parity, with consensus)
     std::vector<hipGraph_t> graph_defs;
@@ -289,6 +301,16 @@ void launch_row_resid(deblur_ctx* c, hipStream_t s, TileRange r) {
     using C = dbl::Cfg<N, WV>;
     hipLaunchKernelGGL((dbl::k_row_resid<N, WV>), dim3(C::RG, r.cnt), dim3(C::NT), 0, s, c->Yc, c->yw, c->tw, c->Rr,
                        c->obj_part, r.t0);
+}
+template <int N, int WV>
+void launch_row_resid_vm(deblur_ctx* c, hipStream_t s, int mode, const float* r_in, float* r_out) {
+    using C = dbl::Cfg<N, WV>;
+    if (mode == 0)
+        hipLaunchKernelGGL((dbl::k_row_resid_vm<N, WV, 0>), dim3(C::RG, c->nt), dim3(C::NT), 0, s, c->Yc, c->yw,
+                           c->tw, r_in, r_out, c->Rr, c->obj_part);
+    else
+        hipLaunchKernelGGL((dbl::k_row_resid_vm<N, WV, 1>), dim3(C::RG, c->nt), dim3(C::NT), 0, s, c->Yc, c->yw,
+                           c->tw, r_in, r_out, c->Rr, c->obj_part);
 }
 template <int N, int WV>
 void launch_col_Ht(deblur_ctx* c, hipStream_t s, TileRange r) {
@@ -500,6 +522,97 @@ void consensus_launch(deblur_ctx* c, hipStream_t s, int parity) {
 
 // Forward row transforms of the current iterate (start of the next step).
 void refresh_spectra(deblur_ctx* c, hipStream_t s) { row_fwd(c, s, c->x[c->cur], c->Zk, 1); }
+
+// ---------------------------------------------------------------------------
+// VMLM-B Local-Solver (vmlmb.h): n iterations on every tile from the current
+// x, with an empty memory at the start.  Each line-search trial ends with a
+// readback of the number of tiles still searching, so this path runs eagerly
+// (no graph capture).
+// ---------------------------------------------------------------------------
+
+void row_resid_vm(deblur_ctx* c, hipStream_t s, int mode, const float* r_in, float* r_out) {
+    DISPATCH_NW(c, c->plan.row_waves, launch_row_resid_vm, s, mode, r_in, r_out);
+}
+
+// Residual, data spectrum and objective change of the trial step in vm_delta.
+void vm_trial_data(deblur_ctx* c, hipStream_t s, const float* r, float* rt) {
+    row_fwd(c, s, c->vm_delta, c->Zk, 1);
+    col_H(c, s);
+    row_resid_vm(c, s, 1, r, rt);
+}
+
+int vmlmb_steps(deblur_ctx* c, int n) {
+    if (n <= 0) return DEBLUR_OK;
+    using namespace dbl;
+    hipStream_t s = c->stream;
+    const size_t fe = frame_elems(c);
+    const SolveParams P = solve_params(c);
+    const dim3 vg(kVmBlocks, c->nt), vb(kVmThreads), tg((c->nt + 255) / 256), tb(256);
+    int* h_search = reinterpret_cast<int*>(c->h_pinned + 32);
+    // residual, row spectrum of W r and prox gradient at the start point
+    row_fwd(c, s, c->x[c->cur], c->Zk, 1);
+    col_H(c, s);
+    row_resid_vm(c, s, 0, nullptr, c->vm_r[c->vm_rc]);
+    col_Ht(c, s);
+    row_inv(c, s, c->Gk, c->frame_tmp, 1);
+    hipLaunchKernelGGL(k_vm_grad, vg, vb, 0, s, c->frame_tmp, c->x[c->cur], c->u, c->tiles, c->omY, c->omX, c->N, P,
+                       c->vm_g[c->vm_gc]);
+    hipLaunchKernelGGL(k_vm_reset, tg, tb, 0, s, c->vm_tile, c->nt);
+    for (int it = 0; it < n; ++it) {
+        float *x = c->x[c->cur], *xt = c->x[1 - c->cur];
+        float *g = c->vm_g[c->vm_gc], *gn = c->vm_g[1 - c->vm_gc];
+        float *r = c->vm_r[c->vm_rc], *rt = c->vm_r[1 - c->vm_rc];
+        // d = -F B (F g) by the two-loop recursion, newest pair first, then
+        // the initial scaling, then oldest first
+        hipLaunchKernelGGL(k_vm_free, vg, vb, 0, s, x, g, c->tiles, c->N, P, c->vm_S, fe, c->vm_tile, c->vm_d,
+                           c->vm_part);
+        for (int j = 0; j < kVmMem; ++j) {
+            hipLaunchKernelGGL(k_vm_coef, tg, tb, 0, s, c->vm_tile, c->vm_part, kVmBlocks, c->nt, j, 0);
+            hipLaunchKernelGGL(k_vm_axpy_dot, vg, vb, 0, s, c->vm_d, c->vm_Y, j, c->vm_S, j + 1 < kVmMem ? j + 1 : -1,
+                               0, c->tiles, c->N, fe, c->vm_tile, c->vm_part);
+        }
+        hipLaunchKernelGGL(k_vm_axpy_dot, vg, vb, 0, s, c->vm_d, c->vm_S, -1, c->vm_Y, kVmMem - 1, 1, c->tiles,
+                           c->N, fe, c->vm_tile, c->vm_part);
+        for (int j = kVmMem - 1; j >= 0; --j) {
+            hipLaunchKernelGGL(k_vm_coef, tg, tb, 0, s, c->vm_tile, c->vm_part, kVmBlocks, c->nt, j, 1);
+            hipLaunchKernelGGL(k_vm_axpy_dot, vg, vb, 0, s, c->vm_d, c->vm_S, j, c->vm_Y, j - 1, 0, c->tiles, c->N,
+                               fe, c->vm_tile, c->vm_part);
+        }
+        hipLaunchKernelGGL(k_vm_direction, vg, vb, 0, s, x, g, c->tiles, c->N, P, c->vm_d);
+        // projected Armijo search, all tiles at once (a tile that is done
+        // recomputes its accepted trial unchanged)
+        hipLaunchKernelGGL(k_vm_ls_init, tg, tb, 0, s, c->vm_tile, c->tau, c->nt);
+        for (int trial = 0; trial < kVmMaxTrials; ++trial) {
+            const int last = trial == kVmMaxTrials - 1;
+            hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, c->vm_search, 0);
+            hipLaunchKernelGGL(k_vm_trial, vg, vb, 0, s, x, c->vm_d, g, c->u, c->tiles, c->omY, c->omX, c->N, P,
+                               c->vm_tile, xt, c->vm_delta, c->vm_part);
+            vm_trial_data(c, s, r, rt);
+            hipLaunchKernelGGL(k_vm_armijo, tg, tb, 0, s, c->vm_tile, c->obj_part, row_groups(c), c->vm_part,
+                               kVmBlocks, c->nt, c->p.lambda, last, c->vm_search);
+            HIP_TRY(c, hipMemcpyAsync(h_search, c->vm_search, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIP_TRY(c, hipStreamSynchronize(s));
+            if (*h_search == 0) break;
+            if (last) {   // the tiles that gave up: their step of length 0
+                hipLaunchKernelGGL(k_vm_trial, vg, vb, 0, s, x, c->vm_d, g, c->u, c->tiles, c->omY, c->omX, c->N,
+                                   P, c->vm_tile, xt, c->vm_delta, c->vm_part);
+                vm_trial_data(c, s, r, rt);
+            }
+        }
+        // gradient at the accepted point, the new pair, the memory
+        col_Ht(c, s);
+        row_inv(c, s, c->Gk, c->frame_tmp, 1);
+        hipLaunchKernelGGL(k_vm_grad, vg, vb, 0, s, c->frame_tmp, xt, c->u, c->tiles, c->omY, c->omX, c->N, P, gn);
+        hipLaunchKernelGGL(k_vm_pair, vg, vb, 0, s, c->vm_delta, gn, g, c->tiles, c->N, fe, c->vm_tile, c->vm_S,
+                           c->vm_Y, c->vm_part);
+        hipLaunchKernelGGL(k_vm_memory, tg, tb, 0, s, c->vm_tile, c->vm_part, kVmBlocks, c->nt);
+        c->cur = 1 - c->cur;
+        c->vm_gc ^= 1;
+        c->vm_rc ^= 1;
+    }
+    refresh_spectra(c, s);
+    return check_launch(c, "vmlmb");
+}
 
 // ---------------------------------------------------------------------------
 // Layout tables
@@ -807,6 +920,21 @@ int alloc_state(deblur_ctx* c) {
         if ((rc = dev_alloc(c, &c->wbuf, fe))) return rc;
         HIP_TRY(c, hipMemsetAsync(c->wbuf, 0, fe * sizeof(float), c->stream));
     }
+    if (c->vmlmb) {
+        // frames are written on the supports only: the rest stays zero
+        for (float** f : {&c->vm_g[0], &c->vm_g[1], &c->vm_r[0], &c->vm_r[1], &c->vm_d, &c->vm_delta}) {
+            if ((rc = dev_alloc(c, f, fe))) return rc;
+            HIP_TRY(c, hipMemsetAsync(*f, 0, fe * sizeof(float), c->stream));
+        }
+        for (float** f : {&c->vm_S, &c->vm_Y}) {
+            if ((rc = dev_alloc(c, f, fe * dbl::kVmMem))) return rc;
+            HIP_TRY(c, hipMemsetAsync(*f, 0, fe * dbl::kVmMem * sizeof(float), c->stream));
+        }
+        if ((rc = dev_alloc(c, &c->vm_tile, c->nt))) return rc;
+        HIP_TRY(c, hipMemsetAsync(c->vm_tile, 0, c->nt * sizeof(dbl::VmTile), c->stream));
+        if ((rc = dev_alloc(c, &c->vm_part, (size_t)3 * c->nt * dbl::kVmBlocks))) return rc;
+        if ((rc = dev_alloc(c, &c->vm_search, 1))) return rc;
+    }
     HIP_TRY(c, hipHostMalloc((void**)&c->h_pinned, 64 * sizeof(double), hipHostMallocDefault));
     // zero everything that is read before being written
     for (float* f : {c->x[0], c->x[1], c->u, c->frame_tmp, c->frame_tmp2})
@@ -952,11 +1080,13 @@ int deblur_create(const deblur_params* params, const float* psfs_host, void* str
     if (p.bc != DEBLUR_BC_NEUMANN && p.bc != DEBLUR_BC_CIRCULAR) return fail(nullptr, DEBLUR_E_ARG, "bc");
     if (!(p.reg_param > 0.f) || !(p.gamma > 0.f) || !(p.lambda >= 0.f) || !(p.rho > 0.f && p.rho < 2.f))
         return fail(nullptr, DEBLUR_E_ARG, "need reg_param > 0, gamma > 0, lambda >= 0, 0 < rho < 2");
-    if (p.local_solver != DEBLUR_SOLVER_PG && p.local_solver != DEBLUR_SOLVER_FISTA)
+    if (p.local_solver != DEBLUR_SOLVER_PG && p.local_solver != DEBLUR_SOLVER_FISTA &&
+        p.local_solver != DEBLUR_SOLVER_VMLMB)
         return fail(nullptr, DEBLUR_E_ARG, "local_solver");
     deblur_ctx* c = new deblur_ctx();
     c->p = p;
     c->fista = p.local_solver == DEBLUR_SOLVER_FISTA;
+    c->vmlmb = p.local_solver == DEBLUR_SOLVER_VMLMB;
     c->stream = static_cast<hipStream_t>(stream);
     int rc = build_layout(c, psfs_host);
     if (rc) {
@@ -1083,6 +1213,7 @@ int deblur_init(deblur_ctx* c, int32_t mode, const float* x0) {
 int deblur_solve_tiles(deblur_ctx* c, int32_t n_inner) {
     if (!c || n_inner < 0) return fail(c, DEBLUR_E_ARG, "bad argument");
     if (!c->have_state) return fail(c, DEBLUR_E_STATE, "deblur_init must come first");
+    if (c->vmlmb) return vmlmb_steps(c, n_inner);
     const hipError_t e = local_steps(c, c->stream, c->aux_stream, n_inner, c->cur);
     if (e != hipSuccess) return fail(c, DEBLUR_E_HIP, std::string("solve_tiles: ") + hipGetErrorString(e));
     if (n_inner & 1) c->cur = 1 - c->cur;
@@ -1104,10 +1235,48 @@ int deblur_consensus(deblur_ctx* c, double* residual) {
     return DEBLUR_OK;
 }
 
+// D-R rounds with the VMLM-B Local-Solver, launched eagerly: round k runs
+// n_inner + growth (first_round + k) VMLM-B iterations, then the consensus
+// step.
+int vmlmb_run(deblur_ctx* c, int n_outer, int n_inner, int growth, int first_round, double tol, double* residuals,
+              int32_t* done) {
+    hipLaunchKernelGGL(dbl::k_set_int, dim3(1), dim3(1), 0, c->stream, c->res_counter, 0);
+    int k = 0;
+    bool nonfinite = false;
+    for (; k < n_outer;) {
+        int rc = vmlmb_steps(c, n_inner + growth * (first_round + k));
+        if (rc) return rc;
+        consensus_launch(c, c->stream, c->cur);
+        if ((rc = check_launch(c, "consensus"))) return rc;
+        ++k;
+        if (tol > 0.0) {
+            HIP_TRY(c, hipMemcpyAsync(c->h_pinned, c->res_last, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            if (!std::isfinite(c->h_pinned[0])) {
+                nonfinite = true;
+                break;
+            }
+            if (c->h_pinned[0] <= tol) break;
+        }
+    }
+    if (residuals && k > 0)
+        HIP_TRY(c, hipMemcpyAsync(residuals, c->res_hist, k * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (done) *done = k;
+    c->round += k;
+    if (nonfinite) return nonfinite_fail(c, "non-finite consensus residual");
+    if (residuals)
+        for (int i = 0; i < k; ++i)
+            if (!std::isfinite(residuals[i]))
+                return nonfinite_fail(c, "non-finite consensus residual in round " + std::to_string(c->round - k + i));
+    return DEBLUR_OK;
+}
+
 int deblur_run(deblur_ctx* c, int32_t n_outer, int32_t n_inner, double tol, double* residuals, int32_t* done) {
     if (!c || n_outer < 0 || n_inner < 0) return fail(c, DEBLUR_E_ARG, "bad argument");
     if (n_outer > kResCap) return fail(c, DEBLUR_E_ARG, "n_outer exceeds 4096");
     if (!c->have_state) return fail(c, DEBLUR_E_STATE, "deblur_init must come first");
+    if (c->vmlmb) return vmlmb_run(c, n_outer, n_inner, 0, 0, tol, residuals, done);
     hipGraphExec_t g[2] = {nullptr, nullptr};
     int rc = ensure_graph(c, n_inner, c->cur, true, &g[c->cur]);
     if (!rc && (n_inner & 1)) rc = ensure_graph(c, n_inner, 1 - c->cur, true, &g[1 - c->cur]);
@@ -1152,6 +1321,7 @@ int deblur_run_schedule(deblur_ctx* c, int32_t n_outer, int32_t n_inner, int32_t
     if (growth == 0) return deblur_run(c, n_outer, n_inner, tol, residuals, done);
     if (n_outer > kResCap) return fail(c, DEBLUR_E_ARG, "n_outer exceeds 4096");
     if (!c->have_state) return fail(c, DEBLUR_E_STATE, "deblur_init must come first");
+    if (c->vmlmb) return vmlmb_run(c, n_outer, n_inner, growth, first_round, tol, residuals, done);
     // one graph of n_inner steps and one of the consensus step alone, per parity
     hipGraphExec_t steps[2] = {nullptr, nullptr}, cons[2] = {nullptr, nullptr};
     int rc = 0;

@@ -8,7 +8,7 @@ REG = {"tv": dl.REG_SMOOTH_TV, "huber": dl.REG_HUBER}
 BC = {"neumann": dl.BC_NEUMANN, "circular": dl.BC_CIRCULAR}
 
 
-SOLVER = {"pg": dl.SOLVER_PG, "fista": dl.SOLVER_FISTA}
+SOLVER = {"pg": dl.SOLVER_PG, "fista": dl.SOLVER_FISTA, "vmlmb": dl.SOLVER_VMLMB}
 
 
 def params_of(problem, fft_size=0, local_solver="pg"):
