@@ -119,13 +119,13 @@ def build_workload(name="batched", tune=True, plan=None, tune_reps=None):
     return ctx, w, scene, psfs, y, W, trials
 
 
-def fista_context(ctx, psfs, y, W):
+def solver_context(ctx, psfs, y, W, local_solver):
     """A second context on the same workload, observation and launch plan,
-    with the FISTA Local-Solver."""
+    with another Local-Solver."""
     import torch
     from paper_1705_06603_amd import _lib as dl
     params = dl.Params.from_buffer_copy(ctx.params)
-    params.local_solver = dl.SOLVER_FISTA
+    params.local_solver = local_solver
     params.fft_size = ctx.tiles[0].frame
     fctx = dl.Context(params, psfs)
     fctx.set_plan(ctx.plan())
@@ -417,13 +417,49 @@ def timed_solves(ctx, w, steps, net=None):
     return e0.elapsed_time(e1) / steps, res
 
 
+def quality_sweep(w, scene, psfs, y, W, plan, lams=(1e-4, 3e-4, 1e-3, 3e-3, 1e-2), rounds=25):
+    """Image quality against the ground truth over a range of lambda, for
+    the proposed method and the independent baseline (no consensus, tiles
+    blended with omega), as Section IV-C compares them: rounds D-R rounds of
+    the workload's Local-Solver steps (the paper reports 25), SNR and SSIM of
+    the observed crop of x_hat against the scene."""
+    import torch
+    from paper_1705_06603_amd import _lib as dl
+    from paper_1705_06603_amd import quality
+    r = w.r
+    truth = scene[r:r + w.M, r:r + w.M]
+    yd = torch.tensor(y.astype(np.float32), device="cuda")
+    Wd = torch.tensor(W.astype(np.float32), device="cuda")
+    out = {"rounds": rounds, "n_inner": w.n_inner, "metric_region": "observed crop, against the scene",
+           "observed": {"snr_db": round(quality.snr_db(y, truth), 4), "ssim": round(quality.ssim(y, truth), 4)},
+           "lambda": list(lams), "proposed": [], "independent": []}
+    for lam in lams:
+        for label, ind in (("proposed", False), ("independent", True)):
+            params = dl.make_params(w.M, w.tiles, w.pitch, w.overlap, w.grid, w.psf_size, lam=lam,
+                                    reg_param=w.eps, gamma=w.gamma, rho=w.rho, independent=ind)
+            params.fft_size = plan.frame
+            c = dl.Context(params, psfs)
+            c.set_plan(plan)
+            c.set_observation(yd, Wd)
+            c.init()
+            c.run(rounds, w.n_inner)
+            xh = c.assemble().cpu().numpy()[r:r + w.M, r:r + w.M]
+            c.close()
+            out[label].append({"snr_db": round(quality.snr_db(xh, truth), 4),
+                               "ssim": round(quality.ssim(xh, truth), 4)})
+    print("# quality sweep done", file=sys.stderr, flush=True)
+    return out
+
+
 def convergence(args):
     """On the batched workload (2048 x 2048): time and iterations to a D-R
     residual of 1e-4 from the plain start, from the network's warm start
-    (with per-tile fallback), with the growing schedule and with the FISTA
-    Local-Solver; plus the FISTA solve throughput.  The network is trained
-    first (untimed) on converged plain-solver pairs (residual 1e-4) of fresh
-    scenes (seeds 10000+), held out from the benchmark scene (seed 2)."""
+    (with per-tile fallback), with the growing schedule, with the FISTA
+    Local-Solver and with the VMLM-B Local-Solver (fixed and growing
+    schedule, the latter the paper's own configuration); plus the FISTA and
+    VMLM-B solve throughput.  The network is trained first (untimed) on
+    converged plain-solver pairs (residual 1e-4) of fresh scenes (seeds
+    10000+), held out from the benchmark scene (seed 2)."""
     import torch
     from paper_1705_06603_amd import _lib as dl
     print("# convergence: batched workload", file=sys.stderr, flush=True)
@@ -435,7 +471,8 @@ def convergence(args):
     trainer.close()
     out = {"workload": WORKLOAD_TEXT["batched"], "tol": 1e-4, "n_inner": w.n_inner, "gamma": w.gamma,
            "plan": ctx.plan().as_dict(), "training": info}
-    fctx = fista_context(ctx, psfs, y, W)
+    fctx = solver_context(ctx, psfs, y, W, dl.SOLVER_FISTA)
+    vctx = solver_context(ctx, psfs, y, W, dl.SOLVER_VMLMB)
     iters = w.n_outer * w.n_inner
     pms, _ = timed_solves(ctx, w, 1)
     pms, _ = timed_solves(ctx, w, 20)
@@ -447,10 +484,16 @@ def convergence(args):
                                "plain_ms_per_solve": round(pms, 3),
                                "plain_value": round((w.M * w.M) * iters / (pms * 1e-3) / 1e6, 2),
                                "unit": UNIT, "row_update_ms": round(fk["row_update"], 5)}
+    timed_solves(vctx, w, 1)
+    vms, _ = timed_solves(vctx, w, 5)
+    out["vmlmb_throughput"] = {"ms_per_solve": round(vms, 3),
+                               "value": round((w.M * w.M) * iters / (vms * 1e-3) / 1e6, 2), "unit": UNIT,
+                               "note": "eager launches, one 4-byte readback per line-search trial"}
     stream = torch.cuda.current_stream()
-    for label in ("plain", "warm", "plain_growing", "plain_fista"):
-        growth = w.n_inner if label == "plain_growing" else 0
-        c = fctx if label == "plain_fista" else ctx
+    growing = ("plain_growing", "vmlmb_growing")
+    for label in ("plain", "warm", "plain_growing", "plain_fista", "plain_vmlmb", "vmlmb_growing"):
+        growth = w.n_inner if label in growing else 0
+        c = fctx if label == "plain_fista" else vctx if "vmlmb" in label else ctx
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -477,6 +520,8 @@ def convergence(args):
     out["network"] = network_cost(ctx, net)
     net.close()
     fctx.close()
+    vctx.close()
+    out["quality_sweep"] = quality_sweep(w, scene, psfs, y, W, ctx.plan())
     ctx.close()
     return out
 

@@ -127,6 +127,13 @@ typedef struct deblur_params {
     float gamma;          /* metric alpha_t = gamma * omega_t, > 0        */
     float rho;            /* D-R relaxation, in (0, 2)                    */
     int32_t local_solver; /* DEBLUR_SOLVER_*                              */
+    int32_t independent;  /* 1: the paper's independent baseline (Section IV):
+                             no consensus; each round sets u_t <- x_t, so
+                             every tile runs the proximal-point method on its
+                             own f_t; deblur_consensus and the rounds of
+                             deblur_run report ||u_new - u_old|| / ||u_new||
+                             and deblur_assemble blends with omega as usual.
+                             0: Algorithm 1 (consensus)                   */
 } deblur_params;
 
 typedef struct deblur_tile_desc {
@@ -205,8 +212,9 @@ int deblur_solve_tiles(deblur_ctx* ctx, int32_t n_inner);
 
 /* Consensus and dual update (Lemma of Section III-B and Algorithm 1):
  * zbar = sum_t omega_t (2 x_t - u_t) / sum_t omega_t over the tiles covering
- * each pixel, u_t <- u_t + rho (zbar - x_t).  *residual_host (may be NULL)
- * receives ||u_new - u_old|| / ||u_new|| over all tiles. */
+ * each pixel, u_t <- u_t + rho (zbar - x_t).  With params.independent = 1
+ * (the independent baseline) the step is u_t <- x_t instead.  *residual_host
+ * (may be NULL) receives ||u_new - u_old|| / ||u_new|| over all tiles. */
 int deblur_consensus(deblur_ctx* ctx, double* residual_host);
 
 /* Algorithm 1: up to n_outer rounds of (n_inner Local-Solver steps +

@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
         ("positivity", ctypes.c_int32), ("fft_size", ctypes.c_int32),
         ("lambda_", ctypes.c_float), ("reg_param", ctypes.c_float),
         ("gamma", ctypes.c_float), ("rho", ctypes.c_float),
-        ("local_solver", ctypes.c_int32),
+        ("local_solver", ctypes.c_int32), ("independent", ctypes.c_int32),
     ]
 
 
@@ -167,7 +167,7 @@ def _stream_handle(stream):
 
 def make_params(M, T, pitch, overlap, G, P, *, model=MODEL_INTERP, reg=REG_SMOOTH_TV, bc=BC_NEUMANN,
                 positivity=True, fft_size=0, lam=1e-3, reg_param=1e-3, gamma=0.4, rho=1.0,
-                M_x=None, T_x=None, G_x=None, local_solver=SOLVER_PG):
+                M_x=None, T_x=None, G_x=None, local_solver=SOLVER_PG, independent=False):
     p = Params()
     p.M_y, p.M_x = M, M if M_x is None else M_x
     p.T_y, p.T_x = T, T if T_x is None else T_x
@@ -177,6 +177,7 @@ def make_params(M, T, pitch, overlap, G, P, *, model=MODEL_INTERP, reg=REG_SMOOT
     p.positivity, p.fft_size = int(bool(positivity)), fft_size
     p.lambda_, p.reg_param, p.gamma, p.rho = lam, reg_param, gamma, rho
     p.local_solver = local_solver
+    p.independent = int(bool(independent))
     return p
 
 

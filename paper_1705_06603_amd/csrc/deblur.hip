@@ -17,6 +17,7 @@
 #include "kernels.h"
 #include "cnn.h"
 #include "vmlmb.h"
+#include "independent.h"
 
 using dbl::Cover;
 using dbl::PackDesc;
@@ -514,8 +515,12 @@ hipError_t local_steps(deblur_ctx* c, hipStream_t s, hipStream_t* aux, int n, in
 }
 
 void consensus_launch(deblur_ctx* c, hipStream_t s, int parity) {
-    hipLaunchKernelGGL(dbl::k_consensus, pix_grid(c), dim3(dbl::kPixBlock), 0, s, c->x[parity], c->u, c->covY,
-                       c->covX, c->Xy, c->Xx, c->p.T_x, c->N, c->p.rho, c->cons_part);
+    if (c->p.independent)   // the independent baseline: u <- x, no exchange between tiles
+        hipLaunchKernelGGL(dbl::k_independent, dim3(c->cons_nparts), dim3(dbl::kIndThreads), 0, s, c->x[parity],
+                           c->u, c->tiles, c->N, c->nt, c->cons_part);
+    else
+        hipLaunchKernelGGL(dbl::k_consensus, pix_grid(c), dim3(dbl::kPixBlock), 0, s, c->x[parity], c->u, c->covY,
+                           c->covX, c->Xy, c->Xx, c->p.T_x, c->N, c->p.rho, c->cons_part);
     hipLaunchKernelGGL(dbl::k_finalize_residual, dim3(1), dim3(dbl::kFinThreads), 0, s, c->cons_part, c->cons_nparts,
                        c->res_hist, c->res_counter, c->res_last, kResCap);
 }
@@ -1083,6 +1088,7 @@ int deblur_create(const deblur_params* params, const float* psfs_host, void* str
     if (p.local_solver != DEBLUR_SOLVER_PG && p.local_solver != DEBLUR_SOLVER_FISTA &&
         p.local_solver != DEBLUR_SOLVER_VMLMB)
         return fail(nullptr, DEBLUR_E_ARG, "local_solver");
+    if (p.independent != 0 && p.independent != 1) return fail(nullptr, DEBLUR_E_ARG, "independent must be 0 or 1");
     deblur_ctx* c = new deblur_ctx();
     c->p = p;
     c->fista = p.local_solver == DEBLUR_SOLVER_FISTA;

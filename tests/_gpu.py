@@ -11,19 +11,19 @@ BC = {"neumann": dl.BC_NEUMANN, "circular": dl.BC_CIRCULAR}
 SOLVER = {"pg": dl.SOLVER_PG, "fista": dl.SOLVER_FISTA, "vmlmb": dl.SOLVER_VMLMB}
 
 
-def params_of(problem, fft_size=0, local_solver="pg"):
+def params_of(problem, fft_size=0, local_solver="pg", independent=False):
     L = problem.layout
     ay, ax = L.ay, L.ax
     return dl.make_params(ay.M, ay.T, ay.p, ay.o, ay.G, 2 * ay.r + 1, model=MODEL[L.model],
                           reg=REG[problem.reg], bc=BC[problem.bc], positivity=problem.positivity,
                           fft_size=fft_size, lam=problem.lam, reg_param=problem.reg_param,
                           gamma=problem.gamma, rho=problem.rho, M_x=ax.M, T_x=ax.T, G_x=ax.G,
-                          local_solver=SOLVER[local_solver])
+                          local_solver=SOLVER[local_solver], independent=independent)
 
 
-def context_of(problem, fft_size=0, observe=True, local_solver="pg"):
+def context_of(problem, fft_size=0, observe=True, local_solver="pg", independent=False):
     import torch
-    ctx = dl.Context(params_of(problem, fft_size, local_solver), problem.psfs)
+    ctx = dl.Context(params_of(problem, fft_size, local_solver, independent), problem.psfs)
     if observe:
         y = torch.tensor(problem.y, dtype=torch.float32, device="cuda").contiguous()
         W = torch.tensor(problem.W, dtype=torch.float32, device="cuda").contiguous()
