@@ -137,37 +137,42 @@ def test_warm_start_falls_back_when_network_does_not_help():
 
 
 def test_trained_warm_start_gains_over_plain_start():
-    """Train briefly on plain-solver pairs of the 256x256 workload, then on a
-    held-out scene the network start is closer to the converged solution
-    than the plain start, and the solve reaches a residual sooner."""
+    """Trained on converged plain-solver pairs (residual 1e-4) of fresh scenes
+    of the 256 x 256 workload's generator, the network starts a held-out
+    scene closer to that scene's converged solution than the plain start,
+    and the warm-started solve reaches residual 1e-4 in fewer rounds."""
     from paper_1705_06603_amd import _lib as dl
     from paper_1705_06603_amd import train as tr
     from paper_1705_06603_amd import workloads
     w = workloads.WORKLOADS["small"]
     ctx, _ = tr.workload_context(w)
     N = ctx.tiles[0].frame
-    ins, outs = tr.make_pairs(ctx, w, seeds=range(100, 108), crop=128, crops_per_tile=4, n_outer=15)
+    ins, outs = tr.make_pairs(ctx, w, seeds=range(100, 108), crop=128, crops_per_tile=4, tol=1e-4,
+                              max_rounds=3000)
     net = dl.Net(16, N, N, seed=11)
     losses = tr.train(net, ins, outs, steps=250, batch=16, lr=2e-3)
-    assert losses[-1] < losses[0]
+    print(f"training loss: first 25 steps {np.mean(losses[:25]):.4e}, last 25 {np.mean(losses[-25:]):.4e}")
+    assert np.mean(losses[-25:]) < np.mean(losses[:25])
     # held-out scene
     tr.observe_scene(ctx, w, 999)
+    res_plain = tr.solve_plain(ctx, w, tol=1e-4, max_rounds=3000)
+    assert res_plain[-1] <= 1e-4
+    x_star = ctx.get_state()[0].cpu().numpy()
     ctx.init()
-    ctx.run(30, w.n_inner)
-    x_star, _ = ctx.get_state()
-    x_star = x_star.cpu().numpy()
-    ctx.init()
-    x_plain, _ = ctx.get_state()
+    x_plain = ctx.get_state()[0].cpu().numpy()
     use, nf = ctx.init_cnn(net)
-    x_warm, _ = ctx.get_state()
-    d_plain = np.linalg.norm(x_plain.cpu().numpy() - x_star)
-    d_warm = np.linalg.norm(x_warm.cpu().numpy() - x_star)
-    print(f"distance to solution: plain {d_plain:.4e} warm {d_warm:.4e}, tiles kept {int(use.sum())}/{len(use)}")
+    x_warm = ctx.get_state()[0].cpu().numpy()
+    d_plain = np.linalg.norm(x_plain - x_star)
+    d_warm = np.linalg.norm(x_warm - x_star)
+    res_warm = []
+    while len(res_warm) < 3000:
+        res_warm += ctx.run(50, w.n_inner, tol=1e-4)
+        if res_warm[-1] <= 1e-4:
+            break
+    print(f"distance to the converged solution: plain {d_plain:.4e} warm {d_warm:.4e}, tiles kept "
+          f"{int(use.sum())}/{len(use)}; rounds to 1e-4: plain {len(res_plain)} warm {len(res_warm)}")
     assert d_warm < d_plain
-    res_w = ctx.run(5, w.n_inner)
-    ctx.init()
-    res_p = ctx.run(5, w.n_inner)
-    print("residuals warm", res_w, "plain", res_p)
+    assert res_warm[-1] <= 1e-4 and len(res_warm) < len(res_plain)
     net.close()
     ctx.close()
 
