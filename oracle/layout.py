@@ -17,6 +17,18 @@ ramps (s + 1/2)/L, s = 0..L-1 from the overlap start.  The half-pixel offset
 keeps omega > 0 so the metric alpha = gamma * omega is positive definite
 (Section III-B needs V positive definite).
 
+Grid layout (Section III-C, smooth shift-variant blur): one tile per PSF
+node, T = G, and block a spans the grid points a - 1 .. a + 1: the pixels
+strictly between c_{a-1} and c_{a+1} (c_k the node centres below), the first
+block from 0 and the last to M.  Adjacent blocks overlap by half an interior
+block, so an observed pixel lies in two blocks per axis (four in 2-D), and
+near a node, within r, the supports of three tiles meet.  The consensus
+weight there is the node's tent widened to reach over its support,
+phi_a(i) = max(0, 1 - |i - c_a| / (q + r + 1/2)), normalised over the tiles
+covering i: omega_a = phi_a / sum_b phi_b.  It is positive on the support
+and sums to one over the covering tiles; between two nodes, where only two
+tiles cover, it is linear.  Requires 2r <= q (at most three tiles meet).
+
 PSF-interpolation weights (Section II-B, first-order interpolation between
 PSFs sampled on a regular grid): G nodes per axis at c_k = (k + 1/2) q - 1/2
 with q = M / G; the tent w_k(i) = max(0, 1 - |i - c_k| / q), held at 1 beyond
@@ -40,11 +52,19 @@ class AxisLayout:
     o: int       # overlap of blocks
     r: int       # PSF half-width
     G: int       # PSF nodes
+    kind: str = "pitch"   # "pitch": blocks from p and o; "grid": one block per node (Section III-C)
 
     def __post_init__(self):
         if self.T < 1 or self.G < 1 or self.r < 0:
             raise ValueError("bad axis layout")
-        if self.T > 1:
+        if self.kind not in ("pitch", "grid"):
+            raise ValueError("kind must be 'pitch' or 'grid'")
+        if self.kind == "grid":
+            if self.T != self.G:
+                raise ValueError("the grid layout has one tile per PSF node")
+            if self.G > 1 and 2 * self.r > self.M / self.G:
+                raise ValueError("the grid layout needs 2r <= the node spacing")
+        elif self.T > 1:
             if self.o + 2 * self.r > self.p:
                 raise ValueError("overlap + 2r must not exceed the pitch")
             if self.M - (self.T - 1) * self.p <= self.o:
@@ -57,6 +77,10 @@ class AxisLayout:
     # --- tiles ------------------------------------------------------------
     def block(self, a):
         """Observed-pixel interval [start, end) of block a."""
+        if self.kind == "grid":
+            start = 0 if a == 0 else int(np.floor(self.node_centre(a - 1))) + 1
+            end = self.M if a == self.T - 1 else int(np.ceil(self.node_centre(a + 1)))
+            return start, end
         start = a * self.p
         end = self.M if a == self.T - 1 else min(a * self.p + self.p + self.o, self.M)
         return start, end
@@ -70,9 +94,21 @@ class AxisLayout:
         s, e = self.support(a)
         return e - s
 
+    def _grid_phi(self, a, coords):
+        h = self.M / self.G + self.r + 0.5
+        return np.maximum(0.0, 1.0 - np.abs(np.asarray(coords, dtype=np.float64) - self.node_centre(a)) / h)
+
     def omega(self, a):
         """Consensus weight of tile a on its support (1-D, float64)."""
         s0, s1 = self.support(a)
+        if self.kind == "grid":
+            coords = np.arange(s0, s1)
+            den = np.zeros(s1 - s0)
+            for b in range(self.T):
+                b0, b1 = self.support(b)
+                inside = (coords >= b0) & (coords < b1)
+                den += np.where(inside, self._grid_phi(b, coords), 0.0)
+            return self._grid_phi(a, coords) / den
         w = np.ones(s1 - s0)
         if a > 0:
             _, prev_end = self.support(a - 1)
@@ -201,10 +237,11 @@ class Layout:
         return y_global[y0:y1, x0:x1].copy()
 
 
-def make_layout(M, T, p, o, P, G, model="interp", M_x=None, T_x=None, G_x=None):
-    """Square-by-default layout helper (P = PSF size 2r+1)."""
+def make_layout(M, T, p, o, P, G, model="interp", M_x=None, T_x=None, G_x=None, kind="pitch"):
+    """Square-by-default layout helper (P = PSF size 2r+1).  kind="grid": the
+    Section III-C layout (one tile per node; p and o unused)."""
     r = P // 2
-    ay = AxisLayout(M, T, p, o, r, G)
+    ay = AxisLayout(M, T, p, o, r, G, kind)
     ax = AxisLayout(M if M_x is None else M_x, T if T_x is None else T_x, p, o, r,
-                    G if G_x is None else G_x)
+                    G if G_x is None else G_x, kind)
     return Layout(ay, ax, model)

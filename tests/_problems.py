@@ -18,8 +18,8 @@ def random_psfs(G_y, G_x, P, seed, positive=True):
 
 def tiny_problem(M=12, T=2, p=6, o=2, P=3, G=2, seed=0, model="interp", lam=1e-2,
                  reg="tv", reg_param=0.05, gamma=0.5, positivity=True, bc="neumann",
-                 W_random=True, M_x=None, T_x=None, G_x=None):
-    L = make_layout(M, T, p, o, P, G, model=model, M_x=M_x, T_x=T_x, G_x=G_x)
+                 W_random=True, M_x=None, T_x=None, G_x=None, kind="pitch"):
+    L = make_layout(M, T, p, o, P, G, model=model, M_x=M_x, T_x=T_x, G_x=G_x, kind=kind)
     rng = np.random.default_rng(seed + 100)
     psfs = random_psfs(L.ay.G, L.ax.G, P, seed)
     My, Mx = L.ay.M, L.ax.M

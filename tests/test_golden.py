@@ -36,6 +36,19 @@ def test_axis_layout_worked_example():
         assert np.allclose(A.tent(k, coords), w, rtol=0, atol=1e-15)
 
 
+def test_grid_axis_layout_worked_example():
+    g = _read("axis_grid_M12_G3_r1.txt")
+    A = AxisLayout(M=12, T=3, p=0, o=0, r=1, G=3, kind="grid")
+    for a, s, e in g["block"]:
+        assert A.block(int(a)) == (int(s), int(e))
+    for a, s, e in g["support"]:
+        assert A.support(int(a)) == (int(s), int(e))
+    for key, coord in (("omega6", 6), ("omega3", 3), ("omegam1", -1)):
+        for a, w in g[key]:
+            s0, _ = A.support(int(a))
+            assert abs(A.omega(int(a))[coord - s0] - w) <= 1e-15, (key, a)
+
+
 def test_smoothed_tv_worked_example():
     g = _read("smoothed_tv_2x2.txt")
     x = np.array(g["x"][0]).reshape(2, 2)
