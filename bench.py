@@ -374,24 +374,34 @@ def warm_network(ctx, w, args):
 
 
 def network_cost(ctx, net):
-    """Forward time of the network on every tile of ctx at once and the MFMA
-    utilisation of a 32 -> 32 layer."""
+    """Forward time of the network on every tile of ctx at once, and its MFMA
+    utilisation: the network's algorithmic flops (38,016 per pixel: layers
+    1 and 4 on the VALU, 2 and 3 on bf16 MFMA) over the launch time, against
+    the dense bf16 MFMA peak.  An inference-only network runs the fused
+    kernel (one launch, activations in LDS); a trainable one runs layer by
+    layer, and then the 32 -> 32 layer alone is reported too."""
     N = ctx.tiles[0].frame
     frames, _ = ctx.warm_inputs()
     B = ctx.n_tiles
     ms_all, ms_mid = net.time_forward(frames, reps=5)
-    flop_mid = 2.0 * 9 * 32 * 32 * B * N * N
-    # the 32 -> 32 layer reads and writes one bf16 activation map of 32
-    # channels: 144 flop per byte, below the bf16 MFMA / HBM balance of
-    # 2500 / 8 = 312, so its roofline is the HBM one
-    bytes_mid = 2.0 * 32 * 2 * B * N * N
-    return {"forward_ms_per_batch": round(ms_all, 3), "batch_tiles": B, "frame": N,
-            "mid_layer_ms": round(ms_mid, 4), "mid_layer_TFLOPs": round(flop_mid / (ms_mid * 1e-3) / 1e12, 1),
-            "mfma_bf16_peak_TFLOPs": 2500.0,
-            "mfma_utilisation": round(flop_mid / (ms_mid * 1e-3) / 2.5e15, 4),
-            "mid_layer_algorithmic_bytes": bytes_mid,
-            "mid_layer_GBps": round(bytes_mid / (ms_mid * 1e-3) / 1e9, 1),
-            "mid_layer_hbm_frac": round(bytes_mid / (ms_mid * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    flop_all = 38016.0 * B * N * N
+    out = {"forward_ms_per_batch": round(ms_all, 3), "batch_tiles": B, "frame": N, "fused": ms_mid == 0.0,
+           "forward_TFLOPs": round(flop_all / (ms_all * 1e-3) / 1e12, 1), "mfma_bf16_peak_TFLOPs": 2500.0,
+           "mfma_utilisation": round(flop_all / (ms_all * 1e-3) / 2.5e15, 4),
+           "activation_hbm_bytes": 0 if ms_mid == 0.0 else 3 * 2 * 64.0 * B * N * N}
+    if ms_mid > 0.0:
+        flop_mid = 2.0 * 9 * 32 * 32 * B * N * N
+        # the 32 -> 32 layer reads and writes one bf16 activation map of 32
+        # channels: 144 flop per byte, below the bf16 MFMA / HBM balance of
+        # 2500 / 8 = 312, so its roofline is the HBM one
+        bytes_mid = 2.0 * 32 * 2 * B * N * N
+        out.update({"mid_layer_ms": round(ms_mid, 4),
+                    "mid_layer_TFLOPs": round(flop_mid / (ms_mid * 1e-3) / 1e12, 1),
+                    "mid_layer_mfma_utilisation": round(flop_mid / (ms_mid * 1e-3) / 2.5e15, 4),
+                    "mid_layer_algorithmic_bytes": bytes_mid,
+                    "mid_layer_GBps": round(bytes_mid / (ms_mid * 1e-3) / 1e9, 1),
+                    "mid_layer_hbm_frac": round(bytes_mid / (ms_mid * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
+    return out
 
 
 def timed_solves(ctx, w, steps, net=None):

@@ -70,6 +70,24 @@ enum {
     DEBLUR_REG_HUBER = 1      /* per-pixel Huber of |Dx| with threshold delta */
 };
 
+/* Block layout (Section III-A, Fig. 1; Section III-C).  PITCH: block a is
+ * [a p, min(a p + p + o, M)), the last one [(T-1) p, M); supports of
+ * neighbours overlap by o + 2r <= p; consensus weights 1 inside a support
+ * and ramps (s + 1/2)/L across each overlap of length L = o + 2r.  GRID (the
+ * smooth shift-variant layout of Section III-C): one block per PSF node
+ * (T = G), spanning the grid points a - 1 .. a + 1 (the pixels strictly
+ * between the node centres c_{a-1} and c_{a+1}, the first block from 0 and
+ * the last to M), so neighbouring blocks overlap by half an interior block
+ * and a pixel lies in two blocks per axis; pitch and overlap are unused;
+ * the operator is each block's own PSF (DEBLUR_MODEL_LOCAL); needs
+ * 2r <= M / G.  Consensus weights: node a's tent widened to reach over its
+ * support, max(0, 1 - |i - c_a| / (M/G + r + 1/2)), normalised over the
+ * (at most three) supports holding pixel i. */
+enum {
+    DEBLUR_LAYOUT_PITCH = 0,
+    DEBLUR_LAYOUT_GRID = 1
+};
+
 enum {
     DEBLUR_BC_NEUMANN = 0,    /* difference 0 at the support's last row/column */
     DEBLUR_BC_CIRCULAR = 1    /* difference wraps within the support           */
@@ -134,6 +152,7 @@ typedef struct deblur_params {
                              deblur_run report ||u_new - u_old|| / ||u_new||
                              and deblur_assemble blends with omega as usual.
                              0: Algorithm 1 (consensus)                   */
+    int32_t layout;       /* DEBLUR_LAYOUT_* (0: pitch / overlap blocks)   */
 } deblur_params;
 
 typedef struct deblur_tile_desc {
@@ -265,7 +284,8 @@ int deblur_step_sizes(deblur_ctx* ctx, float* tau_host);
 
 /* Image formation without noise (Eq. (2)): y = R sum_k Z_k H_k W_k C_k x for a
  * device image x_global on X, written to device y_global [M_y][M_x].  Each
- * observed pixel is taken from the tile whose block owns it. */
+ * observed pixel is taken from the tile whose block owns it (pitch layout
+ * only: DEBLUR_E_STATE for the grid layout). */
 int deblur_blur_global(deblur_ctx* ctx, const float* x_global, float* y_global);
 
 /* Kernel timing on the context stream: reps Local-Solver steps (after one
@@ -398,11 +418,13 @@ typedef struct deblur_cnn deblur_cnn;
  * initialisation (last layer scaled by 0.1).  stream as for deblur_create. */
 int deblur_cnn_create(const float* params_host, int32_t seed, int32_t max_batch, int32_t max_h, int32_t max_w,
                       void* stream, deblur_cnn** out);
-/* The same with forward buffers only (activations of three layers and the
- * output: 3 * 64 + 4 bytes per pixel of max_batch x max_h x max_w), for
- * warm-starting many large tiles in one launch per layer; loss_grad and
- * train_step return DEBLUR_E_STATE on it.  Weights come from params_host
- * (e.g. deblur_cnn_get_params of a trained network). */
+/* The same for inference only: its forward pass is one fused launch (all
+ * four layers of a 28 x 28 output block in one workgroup, the activations in
+ * LDS only; the same values as the layer-by-layer kernels), so it holds the
+ * output alone (4 bytes per pixel of max_batch x max_h x max_w) and
+ * warm-starts many large tiles in one launch; loss_grad and train_step
+ * return DEBLUR_E_STATE on it.  Weights come from params_host (e.g.
+ * deblur_cnn_get_params of a trained network). */
 int deblur_cnn_create_inference(const float* params_host, int32_t seed, int32_t max_batch, int32_t max_h,
                                 int32_t max_w, void* stream, deblur_cnn** out);
 void deblur_cnn_destroy(deblur_cnn* net);
@@ -426,8 +448,10 @@ int deblur_cnn_loss_grad(deblur_cnn* net, const float* img, const float* target,
 int deblur_cnn_train_step(deblur_cnn* net, const float* img, const float* target, int32_t B, int32_t H, int32_t W,
                           float lr, double* loss_host);
 
-/* Mean milliseconds of a whole forward pass and of one 32 -> 32 MFMA layer
- * over reps launches (HIP events on the network stream): ms_host[2]. */
+/* Mean milliseconds over reps launches (HIP events on the network stream):
+ * ms_host[0] of the network's forward pass (fused for an inference-only
+ * network, layer by layer otherwise), ms_host[1] of one layer-by-layer
+ * 32 -> 32 MFMA layer (0 for an inference-only network). */
 int deblur_cnn_time_forward(deblur_cnn* net, const float* img, int32_t B, int32_t H, int32_t W, int32_t reps,
                             float* ms_host);
 

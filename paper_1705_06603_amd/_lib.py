@@ -19,6 +19,7 @@ REG_SMOOTH_TV, REG_HUBER = 0, 1
 BC_NEUMANN, BC_CIRCULAR = 0, 1
 INIT_ZERO, INIT_OBSERVED, INIT_GIVEN = 0, 1, 2
 SOLVER_PG, SOLVER_FISTA, SOLVER_VMLMB = 0, 1, 2
+LAYOUT_PITCH, LAYOUT_GRID = 0, 1
 N_KERNELS = 5
 KERNEL_NAMES = ("col_H", "row_resid", "col_Ht", "row_update", "consensus")
 
@@ -46,6 +47,7 @@ class Params(ctypes.Structure):
         ("lambda_", ctypes.c_float), ("reg_param", ctypes.c_float),
         ("gamma", ctypes.c_float), ("rho", ctypes.c_float),
         ("local_solver", ctypes.c_int32), ("independent", ctypes.c_int32),
+        ("layout", ctypes.c_int32),
     ]
 
 
@@ -167,7 +169,7 @@ def _stream_handle(stream):
 
 def make_params(M, T, pitch, overlap, G, P, *, model=MODEL_INTERP, reg=REG_SMOOTH_TV, bc=BC_NEUMANN,
                 positivity=True, fft_size=0, lam=1e-3, reg_param=1e-3, gamma=0.4, rho=1.0,
-                M_x=None, T_x=None, G_x=None, local_solver=SOLVER_PG, independent=False):
+                M_x=None, T_x=None, G_x=None, local_solver=SOLVER_PG, independent=False, layout=0):
     p = Params()
     p.M_y, p.M_x = M, M if M_x is None else M_x
     p.T_y, p.T_x = T, T if T_x is None else T_x
@@ -178,6 +180,7 @@ def make_params(M, T, pitch, overlap, G, P, *, model=MODEL_INTERP, reg=REG_SMOOT
     p.lambda_, p.reg_param, p.gamma, p.rho = lam, reg_param, gamma, rho
     p.local_solver = local_solver
     p.independent = int(bool(independent))
+    p.layout = layout
     return p
 
 

@@ -16,6 +16,7 @@
 #include "../../include/deblur.h"
 #include "kernels.h"
 #include "cnn.h"
+#include "cnn_fused.h"
 #include "vmlmb.h"
 #include "independent.h"
 
@@ -36,8 +37,14 @@ constexpr double kPsfSumTol = 1e-4;   // accepted |sum of a PSF - 1| (fp32 round
 // One axis of the tiling and of the PSF grid (Section III-A, Fig. 1).
 struct Axis {
     int M, T, p, o, r, G;
+    int kind = DEBLUR_LAYOUT_PITCH;
 
     void block(int a, int& s, int& e) const {
+        if (kind == DEBLUR_LAYOUT_GRID) {   // the pixels strictly between nodes a - 1 and a + 1
+            s = a == 0 ? 0 : (int)std::floor(centre(a - 1)) + 1;
+            e = a == T - 1 ? M : (int)std::ceil(centre(a + 1));
+            return;
+        }
         s = a * p;
         e = (a == T - 1) ? M : std::min(a * p + p + o, M);
     }
@@ -51,10 +58,25 @@ struct Axis {
         support(a, s, e);
         return e - s;
     }
+    // grid layout: node a's tent widened to reach over its support
+    double grid_phi(int a, int coord) const {
+        const double h = (double)M / G + r + 0.5;
+        return std::max(0.0, 1.0 - std::fabs(coord - centre(a)) / h);
+    }
     // consensus weight of tile a at support offset m
     double omega(int a, int m) const {
         int s0, s1;
         support(a, s0, s1);
+        if (kind == DEBLUR_LAYOUT_GRID) {   // normalised over the supports holding the pixel
+            const int coord = s0 + m;
+            double den = 0.0;
+            for (int b = 0; b < T; ++b) {
+                int b0, b1;
+                support(b, b0, b1);
+                if (coord >= b0 && coord < b1) den += grid_phi(b, coord);
+            }
+            return grid_phi(a, coord) / den;
+        }
         double w = 1.0;
         if (a > 0) {
             int ps, pe;
@@ -91,8 +113,16 @@ struct Axis {
         return out;
     }
     std::string validate() const {
-        if (M < 1 || T < 1 || G < 1 || p < 1 || o < 0 || r < 0) return "non-positive size";
-        if (T > 1) {
+        if (kind == DEBLUR_LAYOUT_GRID) {
+            if (M < 1 || T < 1 || G < 1 || r < 0) return "non-positive size";
+            if (T != G) return "the grid layout has one tile per PSF node (T = G)";
+            if (G > 1 && 2.0 * r > (double)M / G) return "the grid layout needs 2r <= the node spacing M / G";
+        } else if (kind != DEBLUR_LAYOUT_PITCH) {
+            return "unknown layout";
+        }
+        if (kind == DEBLUR_LAYOUT_PITCH && (M < 1 || T < 1 || G < 1 || p < 1 || o < 0 || r < 0))
+            return "non-positive size";
+        if (kind == DEBLUR_LAYOUT_PITCH && T > 1) {
             if (o + 2 * r > p) return "overlap + 2r exceeds the pitch";
             if (M - (T - 1) * p <= o) return "last block does not extend past the previous one";
         } else if (p < M && T == 1) {
@@ -626,13 +656,15 @@ int vmlmb_steps(deblur_ctx* c, int n) {
 int build_layout(deblur_ctx* c, const float* psfs_host) {
     const deblur_params& p = c->p;
     c->r = p.P / 2;
-    c->ay = Axis{p.M_y, p.T_y, p.pitch, p.overlap, c->r, p.G_y};
-    c->ax = Axis{p.M_x, p.T_x, p.pitch, p.overlap, c->r, p.G_x};
+    c->ay = Axis{p.M_y, p.T_y, p.pitch, p.overlap, c->r, p.G_y, p.layout};
+    c->ax = Axis{p.M_x, p.T_x, p.pitch, p.overlap, c->r, p.G_x, p.layout};
     std::string e = c->ay.validate();
     if (e.empty()) e = c->ax.validate();
     if (!e.empty()) return fail(nullptr, DEBLUR_E_SHAPE, "geometry: " + e);
     if (p.model == DEBLUR_MODEL_LOCAL && (p.G_y != p.T_y || p.G_x != p.T_x))
         return fail(nullptr, DEBLUR_E_SHAPE, "local model needs one PSF node per tile");
+    if (p.layout == DEBLUR_LAYOUT_GRID && p.model != DEBLUR_MODEL_LOCAL)
+        return fail(nullptr, DEBLUR_E_SHAPE, "the grid layout uses each block's own PSF (DEBLUR_MODEL_LOCAL)");
     c->nt = p.T_y * p.T_x;
     c->nodes = p.G_y * p.G_x;
     c->Xy = p.M_y + 2 * c->r;
@@ -764,24 +796,17 @@ int upload_tables(deblur_ctx* c, const float* psfs_host) {
         std::vector<Cover> cv(Xn);
         for (int I = 0; I < Xn; ++I) {
             const int coord = I - r;
-            Cover cc{-1, 0, -1, 0, 0.f, 0.f, 0, 0};
-            int found = 0;
+            Cover cc{};
             for (int a = 0; a < T; ++a) {
                 int s0, s1;
                 A.support(a, s0, s1);
                 if (coord >= s0 && coord < s1) {
-                    const int m = coord - s0;
-                    const float w = (float)A.omega(a, m);
-                    if (found == 0) {
-                        cc.a0 = a;
-                        cc.m0 = m;
-                        cc.w0 = w;
-                    } else {
-                        cc.a1 = a;
-                        cc.m1 = m;
-                        cc.w1 = w;
+                    if (cc.n < dbl::kMaxCover) {
+                        cc.a[cc.n] = a;
+                        cc.m[cc.n] = coord - s0;
+                        cc.w[cc.n] = (float)A.omega(a, coord - s0);
                     }
-                    ++found;
+                    ++cc.n;
                 }
             }
             cv[I] = cc;
@@ -789,10 +814,12 @@ int upload_tables(deblur_ctx* c, const float* psfs_host) {
         return cv;
     };
     std::vector<Cover> cY = cover_axis(c->ay, p.T_y, c->Xy), cX = cover_axis(c->ax, p.T_x, c->Xx);
-    for (const Cover& cc : cY)
-        if (cc.a0 < 0) return fail(c, DEBLUR_E_SHAPE, "an X row is covered by no tile");
-    for (const Cover& cc : cX)
-        if (cc.a0 < 0) return fail(c, DEBLUR_E_SHAPE, "an X column is covered by no tile");
+    for (const std::vector<Cover>* cv : {&cY, &cX})
+        for (const Cover& cc : *cv) {
+            if (cc.n < 1) return fail(c, DEBLUR_E_SHAPE, "an X row or column is covered by no tile");
+            if (cc.n > dbl::kMaxCover)
+                return fail(c, DEBLUR_E_SHAPE, "an X row or column is covered by more than three tiles");
+        }
 
     std::vector<int> so(2 * c->nt), bo(2 * c->nt), xo(2 * c->nt);
     std::vector<PackDesc> pds(c->nt), pdb(c->nt);
@@ -1443,6 +1470,8 @@ int deblur_step_sizes(deblur_ctx* c, float* tau_host) {
 
 int deblur_blur_global(deblur_ctx* c, const float* xg, float* yg) {
     if (!c || !xg || !yg) return fail(c, DEBLUR_E_ARG, "null argument");
+    if (c->p.layout != DEBLUR_LAYOUT_PITCH)
+        return fail(c, DEBLUR_E_STATE, "deblur_blur_global needs the pitch layout (its blocks own the pixels)");
     hipLaunchKernelGGL(dbl::k_scatter_X, frame_grid(c), dim3(256), 0, c->stream, xg, c->tiles, c->xorg, c->Xx, c->N,
                        c->frame_tmp2);
     apply_H_frames(c, c->stream, c->frame_tmp2, c->frame_tmp);
@@ -1546,8 +1575,8 @@ int deblur_autotune(const deblur_params* params, const float* psfs_host, void* s
         frames.push_back(params->fft_size);
     } else {
         const int r = params->P / 2;
-        const Axis ay{params->M_y, params->T_y, params->pitch, params->overlap, r, params->G_y};
-        const Axis ax{params->M_x, params->T_x, params->pitch, params->overlap, r, params->G_x};
+        const Axis ay{params->M_y, params->T_y, params->pitch, params->overlap, r, params->G_y, params->layout};
+        const Axis ax{params->M_x, params->T_x, params->pitch, params->overlap, r, params->G_x, params->layout};
         int smax = 0;
         for (int a = 0; a < params->T_y; ++a) smax = std::max(smax, ay.support_len(a));
         for (int b = 0; b < params->T_x; ++b) smax = std::max(smax, ax.support_len(b));
@@ -1851,6 +1880,18 @@ void net_forward(deblur_cnn* n, const float* img, int B, int H, int W) {
                        n->master, n->out);
 }
 
+// Forward for inference: the fused kernel (activations in LDS only) for an
+// inference-only network, the layer-by-layer kernels (activations kept for
+// the backward pass) for a trainable one.  Both compute the same values.
+void net_infer(deblur_cnn* n, const float* img, int B, int H, int W) {
+    if (n->trainable) {
+        net_forward(n, img, B, H, W);
+        return;
+    }
+    hipLaunchKernelGGL(K::k_cnn_fwd, K::cnn_fwd_grid(B, H, W), dim3(K::kFusedThreads), 0, n->stream, img, n->desc, H,
+                       W, n->w1, n->wf2, n->wf3, n->w4, n->master, n->out);
+}
+
 // Reduces n->part ([nchunk][ncols]) to one row and scatters it into n->grad.
 void net_reduce(deblur_cnn* n, size_t nchunk, int ncols, int nw, int woff, int nb, int boff, int bsrc) {
     const float* src = n->part;
@@ -1954,11 +1995,11 @@ static int cnn_create(const float* params, int32_t seed, int32_t maxB, int32_t m
     if (!rc) rc = net_alloc(n, &n->w1, 9 * K::C);
     if (!rc) rc = net_alloc(n, &n->w4, 9 * K::C);
     if (!rc) rc = net_alloc(n, &n->desc, maxB);
-    if (!rc) rc = net_alloc(n, &n->a1, px * K::C);
-    if (!rc) rc = net_alloc(n, &n->a2, px * K::C);
-    if (!rc) rc = net_alloc(n, &n->a3, px * K::C);
     if (!rc) rc = net_alloc(n, &n->out, px);
-    if (trainable) {   // backward activations, weight-gradient partials, loss partials
+    if (trainable) {   // activations, backward activations, weight-gradient partials, loss partials
+        if (!rc) rc = net_alloc(n, &n->a1, px * K::C);
+        if (!rc) rc = net_alloc(n, &n->a2, px * K::C);
+        if (!rc) rc = net_alloc(n, &n->a3, px * K::C);
         if (!rc) rc = net_alloc(n, &n->dpA, px * K::C);
         if (!rc) rc = net_alloc(n, &n->dpB, px * K::C);
         if (!rc) rc = net_alloc(n, &n->dout, px);
@@ -2045,7 +2086,7 @@ int deblur_cnn_forward(deblur_cnn* n, const float* img, const int32_t* valid_hos
     if (!rc) rc = net_set_desc(n, B, H, W, valid_host);
     if (rc) return rc;
     net_prep(n);
-    net_forward(n, img, B, H, W);
+    net_infer(n, img, B, H, W);
     HIP_TRY_N(n, hipMemcpyAsync(out, n->out, (size_t)B * H * W * 4, hipMemcpyDeviceToDevice, n->stream));
     return net_check(n, "cnn forward");
 }
@@ -2090,21 +2131,22 @@ int deblur_cnn_time_forward(deblur_cnn* n, const float* img, int32_t B, int32_t 
     HIP_TRY_N(n, hipEventCreate(&e0));
     HIP_TRY_N(n, hipEventCreate(&e1));
     HIP_TRY_N(n, hipEventCreate(&e2));
-    net_forward(n, img, B, H, W);
+    net_infer(n, img, B, H, W);
     HIP_TRY_N(n, hipEventRecord(e0, n->stream));
-    for (int i = 0; i < reps; ++i) net_forward(n, img, B, H, W);
+    for (int i = 0; i < reps; ++i) net_infer(n, img, B, H, W);
     HIP_TRY_N(n, hipEventRecord(e1, n->stream));
     const dim3 mg = K::conv_mid_grid(B, H, W);
-    for (int i = 0; i < reps; ++i)
-        hipLaunchKernelGGL(K::k_conv_mid, mg, dim3(256), 0, n->stream, n->a1, n->desc, H, W, n->wf2,
-                           n->master + K::kB2, nullptr, n->a2);
+    if (n->trainable)   // the layer-by-layer 32 -> 32 layer alone
+        for (int i = 0; i < reps; ++i)
+            hipLaunchKernelGGL(K::k_conv_mid, mg, dim3(256), 0, n->stream, n->a1, n->desc, H, W, n->wf2,
+                               n->master + K::kB2, nullptr, n->a2);
     HIP_TRY_N(n, hipEventRecord(e2, n->stream));
     HIP_TRY_N(n, hipEventSynchronize(e2));
     float t0 = 0.f, t1 = 0.f;
     HIP_TRY_N(n, hipEventElapsedTime(&t0, e0, e1));
     HIP_TRY_N(n, hipEventElapsedTime(&t1, e1, e2));
     ms_host[0] = t0 / reps;
-    ms_host[1] = t1 / reps;
+    ms_host[1] = n->trainable ? t1 / reps : 0.f;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipEventDestroy(e2);
@@ -2147,7 +2189,7 @@ int deblur_init_cnn(deblur_ctx* c, deblur_cnn* n, int32_t* use_cnn_host, int32_t
         const int B = std::min(n->maxB, c->nt - t0);
         int rc = net_set_desc(n, B, N, N, valid.data() + 2 * t0);
         if (rc) return fail(c, rc, n->err);
-        net_forward(n, c->frame_tmp2 + t0 * NN, B, N, N);
+        net_infer(n, c->frame_tmp2 + t0 * NN, B, N, N);
         hipLaunchKernelGGL(K::k_cnn_tile_output, dim3(std::min<int>((int)((NN + 255) / 256), 64), B), dim3(256), 0, s,
                            n->out, c->tile_scale + t0, c->sdim + 2 * t0, N, c->frame_tmp + t0 * NN);
     }

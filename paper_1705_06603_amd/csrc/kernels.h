@@ -40,10 +40,13 @@ struct TileInfo {
     int spec[kMaxK * kMaxK];   // spectrum index of term (ky, kx) at ky * 3 + kx
 };
 
+constexpr int kMaxCover = 3;   // tiles covering one X row or column (3 in the grid layout, near nodes)
 struct Cover {         // tiles covering one X row (or column)
-    int a0, m0, a1, m1;   // tile index and frame coordinate; a1 < 0 if only one
-    float w0, w1;         // consensus weights omega
-    int pad0, pad1;
+    int n;                 // number of covering tiles, 1 .. kMaxCover
+    int a[kMaxCover];      // tile index along the axis
+    int m[kMaxCover];      // frame coordinate in that tile
+    float w[kMaxCover];    // consensus weight omega there
+    int pad[2];
 };
 
 struct SolveParams {
@@ -1050,31 +1053,27 @@ __global__ __launch_bounds__(kPixBlock) void k_consensus(const float* __restrict
     float du2 = 0.f, un2 = 0.f;
     if (J < Xx) {
         const Cover a = cy[I], b = cx[J];
-        const int na = a.a1 >= 0 ? 2 : 1, nb = b.a1 >= 0 ? 2 : 1;
-        size_t idx[4];
-        float xv[4], uv[4];
+        // the weighted average of v = 2x - u over the covering tiles ...
         float num = 0.f, den = 0.f;
-        int k = 0;
-        for (int ia = 0; ia < na; ++ia) {
-            const int ta = ia ? a.a1 : a.a0, m = ia ? a.m1 : a.m0;
-            const float wa = ia ? a.w1 : a.w0;
-            for (int ib = 0; ib < nb; ++ib) {
-                const int tb = ib ? b.a1 : b.a0, c = ib ? b.m1 : b.m0;
-                const float w = wa * (ib ? b.w1 : b.w0);
-                idx[k] = ((size_t)(ta * Tx + tb) * N + m) * N + c;
-                xv[k] = x[idx[k]];
-                uv[k] = u[idx[k]];
-                num += w * (2.f * xv[k] - uv[k]);
+        for (int ia = 0; ia < a.n; ++ia) {
+            for (int ib = 0; ib < b.n; ++ib) {
+                const size_t idx = ((size_t)(a.a[ia] * Tx + b.a[ib]) * N + a.m[ia]) * N + b.m[ib];
+                const float w = a.w[ia] * b.w[ib];
+                num += w * (2.f * x[idx] - u[idx]);
                 den += w;
-                ++k;
             }
         }
         const float zb = num / den;
-        for (int j = 0; j < k; ++j) {
-            const float un = uv[j] + rho * (zb - xv[j]);
-            u[idx[j]] = un;
-            du2 += (un - uv[j]) * (un - uv[j]);
-            un2 += un * un;
+        // ... then the dual update of each covering tile (x and u re-read from cache)
+        for (int ia = 0; ia < a.n; ++ia) {
+            for (int ib = 0; ib < b.n; ++ib) {
+                const size_t idx = ((size_t)(a.a[ia] * Tx + b.a[ib]) * N + a.m[ia]) * N + b.m[ib];
+                const float uo = u[idx];
+                const float un = uo + rho * (zb - x[idx]);
+                u[idx] = un;
+                du2 += (un - uo) * (un - uo);
+                un2 += un * un;
+            }
         }
     }
     const float2 s = block_sum2(make_float2(du2, un2), red, tid);
@@ -1133,15 +1132,11 @@ __global__ __launch_bounds__(kPixBlock) void k_assemble(const float* __restrict_
     const int J = blockIdx.x * kPixBlock + threadIdx.x, I = blockIdx.y;
     if (J >= Xx) return;
     const Cover a = cy[I], b = cx[J];
-    const int na = a.a1 >= 0 ? 2 : 1, nb = b.a1 >= 0 ? 2 : 1;
     float num = 0.f, den = 0.f;
-    for (int ia = 0; ia < na; ++ia) {
-        const int ta = ia ? a.a1 : a.a0, m = ia ? a.m1 : a.m0;
-        const float wa = ia ? a.w1 : a.w0;
-        for (int ib = 0; ib < nb; ++ib) {
-            const int tb = ib ? b.a1 : b.a0, c = ib ? b.m1 : b.m0;
-            const float w = wa * (ib ? b.w1 : b.w0);
-            num += w * x[((size_t)(ta * Tx + tb) * N + m) * N + c];
+    for (int ia = 0; ia < a.n; ++ia) {
+        for (int ib = 0; ib < b.n; ++ib) {
+            const float w = a.w[ia] * b.w[ib];
+            num += w * x[((size_t)(a.a[ia] * Tx + b.a[ib]) * N + a.m[ia]) * N + b.m[ib]];
             den += w;
         }
     }

@@ -18,7 +18,8 @@ def params_of(problem, fft_size=0, local_solver="pg", independent=False):
                           reg=REG[problem.reg], bc=BC[problem.bc], positivity=problem.positivity,
                           fft_size=fft_size, lam=problem.lam, reg_param=problem.reg_param,
                           gamma=problem.gamma, rho=problem.rho, M_x=ax.M, T_x=ax.T, G_x=ax.G,
-                          local_solver=SOLVER[local_solver], independent=independent)
+                          local_solver=SOLVER[local_solver], independent=independent,
+                          layout=dl.LAYOUT_GRID if ay.kind == "grid" else dl.LAYOUT_PITCH)
 
 
 def context_of(problem, fft_size=0, observe=True, local_solver="pg", independent=False):

@@ -195,3 +195,35 @@ def test_inference_only_network():
     assert e.value.code == -5
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_fused_forward_equals_layer_by_layer_and_matches_oracle(seed):
+    """The fused forward kernel (inference-only network: all four layers of a
+    28 x 28 block in one workgroup, activations in LDS) against the
+    layer-by-layer kernels (trainable network) on images whose size and valid
+    regions cut the 28-pixel blocks unevenly, and against the bf16 oracle."""
+    import torch
+    from paper_1705_06603_amd import _lib as dl
+    flat = _params(seed)
+    B, H, W = 3, 96, 160
+    valid = [[96, 160], [70, 150], [29, 31]]
+    rng = np.random.default_rng(seed)
+    img = (3.0 * rng.random((B, H, W))).astype(np.float32)
+    a = dl.Net(B, H, W, params=flat)
+    b = dl.Net(B, H, W, params=flat, inference_only=True)
+    t = torch.tensor(img, device="cuda")
+    oa = a.forward(t, valid=valid).cpu().numpy()
+    ob = b.forward(t, valid=valid).cpu().numpy()
+    diff = float(np.max(np.abs(oa - ob)))
+    print(f"fused vs layer by layer: max |difference| {diff:.3e}, identical {np.array_equal(oa, ob)}")
+    assert diff <= 1e-6 * float(np.max(np.abs(oa)))
+    P = cnn.unflatten(flat.astype(np.float64))
+    for k, (vh, vw) in enumerate(valid):
+        x = img[k:k + 1, :vh, :vw].astype(np.float64)
+        ref16, _ = cnn.forward(P, x, bf16=True)
+        assert _rel(ob[k, :vh, :vw], ref16[0]) <= 5e-3
+        assert np.all(ob[k, vh:, :] == 0) and np.all(ob[k, :, vw:] == 0)
+    a.close()
+    b.close()
+

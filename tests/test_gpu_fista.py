@@ -19,17 +19,21 @@ def test_fista_inner_steps_match_oracle(reg, bc):
     x0 = [rng.random(L.support_shape(t)) for t in range(L.n_tiles)]
     u0 = [rng.random(L.support_shape(t)) for t in range(L.n_tiles)]
     tau = ctx.step_sizes()
+    worst = 0.0
     for n in (1, 3, 6):
         ctx.set_state(to_dev(ctx.pack_list_support(x0)), to_dev(ctx.pack_list_support(u0)))
         ctx.solve_tiles(n)
         xg = ctx.unpack_support(ctx.get_state()[0].cpu().numpy())
         for t in range(L.n_tiles):
             ref = solver.local_solve(prob, t, _f32(x0[t]), _f32(u0[t]), n, float(tau[t]), "fista")
-            assert rel_l2(xg[t], ref) <= 2e-5 * n, (n, t, rel_l2(xg[t], ref))
+            err = rel_l2(xg[t], ref)
+            worst = max(worst, err / n)
+            assert err <= 1e-5 * n, (n, t, err)
             # FISTA and plain projected gradient part ways after two steps
             if n == 6:
                 pg = solver.local_solve(prob, t, _f32(x0[t]), _f32(u0[t]), n, float(tau[t]), "pg")
                 assert rel_l2(ref, pg) > 100 * rel_l2(xg[t], ref)
+    print(f"FISTA inner steps ({reg}/{bc}): worst rel L2 per step {worst:.2e}")
     ctx.close()
 
 
