@@ -364,57 +364,71 @@ __global__ __launch_bounds__(256) void k_bwd_out(const float* __restrict__ dout,
     }
 }
 
-// Weight gradient of a 32 -> 32 layer over one chunk of pixels (8 rows x 32
-// columns of one image): part[chunk][co][ci][tap] = sum_p dp[p][co] a[p + tap][ci],
-// and part[chunk][9216 + co] = sum_p dp[p][co].  256 threads: thread =
-// (co = tid / 8, four input channels 4 (tid mod 8) .. + 3), 36 sums each.
 constexpr int kWgRows = 8, kWgCols = 32;
+
+// Weight gradient of a 32 -> 32 layer over one chunk of kWgRows x kWgCols
+// output pixels, on MFMA: for each tap t, dW_t[co][ci] = sum_p dp[p][co]
+// a[p + t][ci] is a 32 x 32 x 256 product with K = the chunk's pixels (bf16
+// operands, fp32 accumulation), one 32-pixel chunk row per k step.  Wave w
+// owns the output block (co half w mod 2, ci half w / 2) for all 9 taps.
+// LDS holds dp transposed, [co][p], and three copies of the halo of a
+// transposed and pre-shifted by dx, [dx][ci][row][px] = a(row, px + dx), so
+// every operand fragment (8 consecutive pixels of one channel) is one
+// aligned 16-byte read.  part[chunk] = (dW as [co][ci][t], then sum_p dp[p][co]).
 __global__ __launch_bounds__(256) void k_wgrad_mid(const unsigned short* __restrict__ dp,
                                                    const unsigned short* __restrict__ a,
                                                    const ImgDesc* __restrict__ desc, int H, int W,
                                                    float* __restrict__ part) {
-    __shared__ float sdp[kWgRows * kWgCols][C + 1];
-    __shared__ float sa[(kWgRows + 2) * (kWgCols + 2)][C + 1];
+    constexpr int P = kWgRows * kWgCols;
+    __shared__ __attribute__((aligned(16))) unsigned short sdpT[C][P];
+    __shared__ __attribute__((aligned(16))) unsigned short saT[3][C][kWgRows + 2][kWgCols];
     const int b = blockIdx.z, y0 = blockIdx.y * kWgRows, x0 = blockIdx.x * kWgCols;
     const ImgDesc d = desc[b];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < kWgRows * kWgCols * C; e += 256) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int e = tid; e < P * C; e += 256) {
         const int p = e / C, c = e % C;
         const int yy = y0 + p / kWgCols, xs = x0 + p % kWgCols;
-        sdp[p][c] = inside(d, yy, xs) ? bf2f(dp[(((size_t)b * H + yy) * W + xs) * C + c]) : 0.f;
+        sdpT[c][p] = inside(d, yy, xs) ? dp[(((size_t)b * H + yy) * W + xs) * C + c] : (unsigned short)0;
     }
     for (int e = tid; e < (kWgRows + 2) * (kWgCols + 2) * C; e += 256) {
-        const int p = e / C, c = e % C;
-        const int yy = y0 + p / (kWgCols + 2) - 1, xs = x0 + p % (kWgCols + 2) - 1;
-        sa[p][c] = inside(d, yy, xs) ? bf2f(a[(((size_t)b * H + yy) * W + xs) * C + c]) : 0.f;
+        const int hp = e / C, c = e % C;
+        const int hy = hp / (kWgCols + 2), hx = hp % (kWgCols + 2);
+        const int yy = y0 + hy - 1, xs = x0 + hx - 1;
+        const unsigned short v = inside(d, yy, xs) ? a[(((size_t)b * H + yy) * W + xs) * C + c] : (unsigned short)0;
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            const int px = hx - dx;
+            if (px >= 0 && px < kWgCols) saT[dx][c][hy][px] = v;
+        }
     }
     __syncthreads();
-    const int co = tid >> 3, cq = (tid & 7) * 4;
-    float acc[9][4];
+    const int co0 = 16 * (wave & 1), ci0 = 16 * (wave >> 1);
+    f32x4 acc[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t)
+    for (int t = 0; t < 9; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int g = 0; g < kWgRows; ++g) {
+        const bf16x8 A = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&sdpT[co0 + li][g * kWgCols + 8 * lk]));
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[t][j] = 0.f;
-    float bsum = 0.f;
-    for (int py = 0; py < kWgRows; ++py) {
-        for (int px = 0; px < kWgCols; ++px) {
-            const float g = sdp[py * kWgCols + px][co];
-            bsum += g;
-#pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const float* ar = sa[(py + t / 3) * (kWgCols + 2) + px + t % 3];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[t][j] += g * ar[cq + j];
-            }
+        for (int t = 0; t < 9; ++t) {
+            const uint4 bv = *reinterpret_cast<const uint4*>(&saT[t % 3][ci0 + li][g + t / 3][8 * lk]);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(bf16x8, bv), acc[t], 0, 0, 0);
         }
     }
     const size_t chunk = ((size_t)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     float* pp = part + chunk * (9 * C * C + C);
+    // D: column ci0 + li, rows (co) co0 + 4 lk .. + 3
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int q = 0; q < 4; ++q) {
+        const int co = co0 + 4 * lk + q, ci = ci0 + li;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) pp[(co * C + cq + j) * 9 + t] = acc[t][j];
-    if ((tid & 7) == 0) pp[9 * C * C + co] = bsum;
+        for (int t = 0; t < 9; ++t) pp[(co * C + ci) * 9 + t] = acc[t][q];
+    }
+    if (tid < C) {
+        float bsum = 0.f;
+        for (int p = 0; p < P; ++p) bsum += bf2f(sdpT[tid][p]);
+        pp[9 * C * C + tid] = bsum;
+    }
 }
 
 // Weight gradients of the 1 -> 32 and 32 -> 1 layers over one chunk:

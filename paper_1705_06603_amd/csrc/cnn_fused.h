@@ -63,7 +63,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_cnn_fwd(const float* __restri
                                                           float* __restrict__ out) {
     __shared__ __attribute__((aligned(16))) unsigned short bufA[kBufA];
     __shared__ __attribute__((aligned(16))) unsigned short bufB[kBufB];
-    __shared__ float sw1[9 * C + C], sw4[9 * C];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lk = lane >> 4;
     const int b = blockIdx.z, Y0 = blockIdx.y * kTile, X0 = blockIdx.x * kTile;
@@ -77,11 +76,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_cnn_fwd(const float* __restri
         }
         return;
     }
-    for (int i = tid; i < 9 * C; i += kFusedThreads) {
-        sw1[i] = w1[i];
-        sw4[i] = w4[i];
-    }
-    for (int i = tid; i < C; i += kFusedThreads) sw1[9 * C + i] = master[kB1 + i];
     // x region (bf16-rounded, 0 outside the valid region) into buffer B
     float* xs = reinterpret_cast<float*>(bufB);
     for (int e = tid; e < kR0 * kR0; e += kFusedThreads) {
@@ -90,9 +84,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_cnn_fwd(const float* __restri
     }
     __syncthreads();
     // layer 1: a1 = bf16(relu(b1 + sum_t w1[t] x)) on the a1 region
+    // the weights of layers 1 and 4 are read from global memory at addresses
+    // uniform across the workgroup, so they come in through the scalar cache
+    // as SGPR operands
+    const float* __restrict__ b1 = master + kB1;
     for (int e = tid; e < kR1 * kR1; e += kFusedThreads) {
-        // keeps the weight reads inside the pixel loop (not hoisted into registers)
-        asm volatile("" ::: "memory");
         const int r = e / kR1, cc = e % kR1;
         unsigned int* o = reinterpret_cast<unsigned int*>(bufA + e * C);
         if (!inside(d, Y0 - 3 + r, X0 - 3 + cc)) {
@@ -104,11 +100,11 @@ __global__ __launch_bounds__(kFusedThreads) void k_cnn_fwd(const float* __restri
         for (int t = 0; t < 9; ++t) in[t] = xs[(r + t / 3) * kR0 + cc + t % 3];
 #pragma unroll 4
         for (int co = 0; co < C; co += 2) {
-            float s0 = sw1[9 * C + co], s1 = sw1[9 * C + co + 1];
+            float s0 = b1[co], s1 = b1[co + 1];
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
-                s0 += sw1[t * C + co] * in[t];
-                s1 += sw1[t * C + co + 1] * in[t];
+                s0 += w1[t * C + co] * in[t];
+                s1 += w1[t * C + co + 1] * in[t];
             }
             o[co / 2] = (unsigned int)f2bf(fmaxf(s0, 0.f)) | ((unsigned int)f2bf(fmaxf(s1, 0.f)) << 16);
         }
@@ -149,7 +145,6 @@ __global__ __launch_bounds__(kFusedThreads) void k_cnn_fwd(const float* __restri
     }
     // layer 4 and the residual: out = x + b4 + sum_t w4[t] . a3
     for (int e = tid; e < kTile * kTile; e += kFusedThreads) {
-        asm volatile("" ::: "memory");
         const int r = e / kTile, cc = e % kTile;
         const int y = Y0 + r, xx = X0 + cc;
         if (y >= H || xx >= W) continue;
@@ -169,8 +164,8 @@ __global__ __launch_bounds__(kFusedThreads) void k_cnn_fwd(const float* __restri
 #pragma unroll
                 for (int e2 = 0; e2 < 4; ++e2) {
                     const int c = 8 * q + 2 * e2;
-                    s += sw4[t * C + c] * bf2f((unsigned short)(w[e2] & 0xFFFF)) +
-                         sw4[t * C + c + 1] * bf2f((unsigned short)(w[e2] >> 16));
+                    s += w4[t * C + c] * bf2f((unsigned short)(w[e2] & 0xFFFF)) +
+                         w4[t * C + c + 1] * bf2f((unsigned short)(w[e2] >> 16));
                 }
             }
         }

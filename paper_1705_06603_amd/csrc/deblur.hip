@@ -223,6 +223,7 @@ struct deblur_ctx {
     double* vm_part = nullptr;    // VMLM-B: per-block partial sums
     int* vm_search = nullptr;     // VMLM-B: tiles still searching
     int vm_gc = 0, vm_rc = 0;     // current gradient / residual buffer
+    int max_cover = 2;            // the most tiles covering an X row or column
     std::vector<void*> allocs;
     std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;   // (steps, parity, with consensus)
     std::vector<hipGraph_t> graph_defs;
@@ -549,7 +550,7 @@ void consensus_launch(deblur_ctx* c, hipStream_t s, int parity) {
         hipLaunchKernelGGL(dbl::k_independent, dim3(c->cons_nparts), dim3(dbl::kIndThreads), 0, s, c->x[parity],
                            c->u, c->tiles, c->N, c->nt, c->cons_part);
     else
-        hipLaunchKernelGGL(dbl::k_consensus, pix_grid(c), dim3(dbl::kPixBlock), 0, s, c->x[parity], c->u, c->covY,
+        hipLaunchKernelGGL(c->max_cover > 2 ? dbl::k_consensus<3> : dbl::k_consensus<2>, pix_grid(c), dim3(dbl::kPixBlock), 0, s, c->x[parity], c->u, c->covY,
                            c->covX, c->Xy, c->Xx, c->p.T_x, c->N, c->p.rho, c->cons_part);
     hipLaunchKernelGGL(dbl::k_finalize_residual, dim3(1), dim3(dbl::kFinThreads), 0, s, c->cons_part, c->cons_nparts,
                        c->res_hist, c->res_counter, c->res_last, kResCap);
@@ -819,6 +820,7 @@ int upload_tables(deblur_ctx* c, const float* psfs_host) {
             if (cc.n < 1) return fail(c, DEBLUR_E_SHAPE, "an X row or column is covered by no tile");
             if (cc.n > dbl::kMaxCover)
                 return fail(c, DEBLUR_E_SHAPE, "an X row or column is covered by more than three tiles");
+            c->max_cover = std::max(c->max_cover, cc.n);
         }
 
     std::vector<int> so(2 * c->nt), bo(2 * c->nt), xo(2 * c->nt);
@@ -1519,7 +1521,7 @@ int deblur_time_kernels(deblur_ctx* c, int32_t reps, float* ms) {
     hipLaunchKernelGGL(dbl::k_copy, dim3(1024), dim3(256), 0, c->stream, c->frame_tmp2, c->x[cur], frame_elems(c));
     // consensus step, repeated on the same (x, u)
     auto cons = [&]() {
-        hipLaunchKernelGGL(dbl::k_consensus, pix_grid(c), dim3(dbl::kPixBlock), 0, c->stream, c->x[cur], c->u, c->covY,
+        hipLaunchKernelGGL(c->max_cover > 2 ? dbl::k_consensus<3> : dbl::k_consensus<2>, pix_grid(c), dim3(dbl::kPixBlock), 0, c->stream, c->x[cur], c->u, c->covY,
                            c->covX, c->Xy, c->Xx, c->p.T_x, c->N, c->p.rho, c->cons_part);
     };
     cons();

@@ -1043,6 +1043,9 @@ __device__ __forceinline__ float2 block_sum2(float2 v, float2* red, int tid) {
 
 // zbar = sum omega (2x - u) / sum omega over covering tiles; u += rho (zbar - x).
 // part[block] = (sum (u_new - u_old)^2, sum u_new^2) over the pixels' tile copies.
+// MAXC: the most tiles covering an X row or column (2 in the pitch layout,
+// 3 in the grid layout), a compile-time bound for the per-pixel arrays.
+template <int MAXC>
 __global__ __launch_bounds__(kPixBlock) void k_consensus(const float* __restrict__ x, float* __restrict__ u,
                                                         const Cover* __restrict__ cy, const Cover* __restrict__ cx,
                                                         int Xy, int Xx, int Tx, int N, float rho,
@@ -1053,27 +1056,33 @@ __global__ __launch_bounds__(kPixBlock) void k_consensus(const float* __restrict
     float du2 = 0.f, un2 = 0.f;
     if (J < Xx) {
         const Cover a = cy[I], b = cx[J];
-        // the weighted average of v = 2x - u over the covering tiles ...
+        size_t idx[MAXC * MAXC];
+        float xv[MAXC * MAXC], uv[MAXC * MAXC];
         float num = 0.f, den = 0.f;
-        for (int ia = 0; ia < a.n; ++ia) {
-            for (int ib = 0; ib < b.n; ++ib) {
-                const size_t idx = ((size_t)(a.a[ia] * Tx + b.a[ib]) * N + a.m[ia]) * N + b.m[ib];
+        int k = 0;
+#pragma unroll
+        for (int ia = 0; ia < MAXC; ++ia) {
+            if (ia >= a.n) break;
+#pragma unroll
+            for (int ib = 0; ib < MAXC; ++ib) {
+                if (ib >= b.n) break;
                 const float w = a.w[ia] * b.w[ib];
-                num += w * (2.f * x[idx] - u[idx]);
+                idx[k] = ((size_t)(a.a[ia] * Tx + b.a[ib]) * N + a.m[ia]) * N + b.m[ib];
+                xv[k] = x[idx[k]];
+                uv[k] = u[idx[k]];
+                num += w * (2.f * xv[k] - uv[k]);
                 den += w;
+                ++k;
             }
         }
         const float zb = num / den;
-        // ... then the dual update of each covering tile (x and u re-read from cache)
-        for (int ia = 0; ia < a.n; ++ia) {
-            for (int ib = 0; ib < b.n; ++ib) {
-                const size_t idx = ((size_t)(a.a[ia] * Tx + b.a[ib]) * N + a.m[ia]) * N + b.m[ib];
-                const float uo = u[idx];
-                const float un = uo + rho * (zb - x[idx]);
-                u[idx] = un;
-                du2 += (un - uo) * (un - uo);
-                un2 += un * un;
-            }
+#pragma unroll
+        for (int j = 0; j < MAXC * MAXC; ++j) {
+            if (j >= k) break;
+            const float un = uv[j] + rho * (zb - xv[j]);
+            u[idx[j]] = un;
+            du2 += (un - uv[j]) * (un - uv[j]);
+            un2 += un * un;
         }
     }
     const float2 s = block_sum2(make_float2(du2, un2), red, tid);
