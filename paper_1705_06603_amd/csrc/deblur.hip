@@ -792,6 +792,17 @@ int upload_tables(deblur_ctx* c, const float* psfs_host) {
     };
     fill_axis(c->ay, p.T_y, tY, oY);
     fill_axis(c->ax, p.T_x, tX, oX);
+    // the column kernels read the y tents lane-major: row l + LPL s of a
+    // tent row (LPL = N / 20 lanes per column, s < 20) at l * 20 + s
+    {
+        const int LPL = N / dbl::kV;
+        std::vector<float> row(N);
+        for (size_t base = 0; base < tY.size(); base += N) {
+            for (int l = 0; l < LPL; ++l)
+                for (int s = 0; s < dbl::kV; ++s) row[(size_t)l * dbl::kV + s] = tY[base + l + (size_t)LPL * s];
+            std::copy(row.begin(), row.end(), tY.begin() + base);
+        }
+    }
     // coverage of X rows / columns
     auto cover_axis = [&](const Axis& A, int T, int Xn) {
         std::vector<Cover> cv(Xn);

@@ -482,6 +482,25 @@ __device__ __forceinline__ void load_spec(float2 (&sp)[kV], const float2* __rest
     for (int s = 0; s < kV; ++s) sp[s] = bl[slot_const<N, RL>(s)];
 }
 
+// Loads the y-tent values of the lane's 20 column slots.  The table is kept
+// lane-major: row l + LPL s of a tent row is stored at l kV + s, so a lane's
+// values are 80 contiguous bytes, five 16-byte loads.
+// Q0 .. Q1 - 1 select a part of the five loads (slots 4 Q0 .. 4 Q1 - 1).
+template <int N, int Q0 = 0, int Q1 = kV / 4>
+__device__ __forceinline__ void load_tent_col(float (&a)[kV], const float* __restrict__ row, int lane) {
+    constexpr int LPL = lanes_per_line<N>();
+    static_assert(nat_radix<N>() == kV, "the column slots of a lane must be rows l + LPL s");
+    const float4* __restrict__ p = reinterpret_cast<const float4*>(row + (lane % LPL) * kV);
+#pragma unroll
+    for (int q = Q0; q < Q1; ++q) {
+        const float4 f = p[q];
+        a[4 * q] = f.x;
+        a[4 * q + 1] = f.y;
+        a[4 * q + 2] = f.z;
+        a[4 * q + 3] = f.w;
+    }
+}
+
 // H: Yc[f][:] = IFFT_col( sum_{ky,kx} spec_k . FFT_col(a_ky . Z_kx[f][:]) )
 template <int N, int WV>
 __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_H(const float2* __restrict__ Zk, const TileInfo* __restrict__ tiles,
@@ -516,18 +535,19 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_H(const float2* __rest
         {
             const int ln = fresh_lane(lane);
             const float2* __restrict__ zl = zt + slot_base<N>(ln, ls);
-            const float* __restrict__ al = am + ln % LPL;
+            float a[kV];
+            load_tent_col<N>(a, am, ln);
             if (special) {
 #pragma unroll
                 for (int s = 0; s < kV; ++s) {
                     constexpr int R = nat_radix<N>();
-                    v[s] = cscale(col_in(zl[slot_const<N, R>(s)], mode), al[slot_const<N, R>(s)]);
+                    v[s] = cscale(col_in(zl[slot_const<N, R>(s)], mode), a[s]);
                 }
             } else {
 #pragma unroll
                 for (int s = 0; s < kV; ++s) {
                     constexpr int R = nat_radix<N>();
-                    v[s] = cscale(zl[slot_const<N, R>(s)], al[slot_const<N, R>(s)]);
+                    v[s] = cscale(zl[slot_const<N, R>(s)], a[s]);
                 }
             }
         }
@@ -583,10 +603,16 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_Ht(const float2* __res
         fft_passes<N, kInv>(v, sw, tw + C::TWC_F, lane);
         const float* am = tentY + ((size_t)ty * kMaxK + ky) * N;
         {
-            const int ln = fresh_lane(lane);
-            const float* __restrict__ al = am + ln % LPL;
+            // in two parts, so that the tents of the second part are loaded
+            // into registers the first part's products have freed
+            float a[kV];
+            load_tent_col<N, 0, 3>(a, am, fresh_lane(lane));
 #pragma unroll
-            for (int s = 0; s < kV; ++s) acc[s] = cadd(acc[s], cscale(v[s], al[slot_const<N, nat_radix<N>()>(s)]));
+            for (int s = 0; s < 12; ++s) acc[s] = cadd(acc[s], cscale(v[s], a[s]));
+            __builtin_amdgcn_sched_barrier(0);
+            load_tent_col<N, 3, 5>(a, am, fresh_lane(lane));
+#pragma unroll
+            for (int s = 12; s < kV; ++s) acc[s] = cadd(acc[s], cscale(v[s], a[s]));
         }
         if (ky == nky - 1) {
             const int ln = fresh_lane(lane);
