@@ -431,36 +431,86 @@ def timed_solves(ctx, w, steps, net=None):
     return e0.elapsed_time(e1) / steps, res
 
 
-def quality_sweep(w, scene, psfs, y, W, plan, lams=(1e-4, 3e-4, 1e-3, 3e-3, 1e-2), rounds=25):
+# The lambda sweep of Section IV on a natural-image stand-in: a dead-leaves
+# scene with the batched workload's geometry (2048^2, 8 x 8 tiles of pitch
+# 256, 32-px overlap), an 8 x 8 grid of 31 x 31 elliptical Gaussian PSFs
+# growing radially from FWHM 3.5 px to 8.5 x 6.5 px (the milder of the
+# paper's two shift-variant grids), white Gaussian noise of variance 400 on
+# a 6000-photon peak (sigma = 1/300 on the unit-peak scene), the Huber prior
+# on circular differences with delta = 100 photons (1/60).  In these units
+# the paper's lambda (photon scale, W = 1/400) is lambda / 400.
+QUALITY = dict(M=2048, tiles=8, pitch=256, overlap=32, grid=8, psf=31, sigma=1.0 / 300.0, delta=1.0 / 60.0,
+               gamma=4.0, seed=4, tol=1e-4, max_rounds=400)
+
+
+def quality_sweep(plan, lams_paper=(1.5625e-5, 3.125e-5, 6.25e-5, 1.25e-4, 2.5e-4, 5e-4, 1e-3),
+                  overlaps=(0, 16, 32, 64)):
     """Image quality against the ground truth over a range of lambda, for
     the proposed method and the independent baseline (no consensus, tiles
-    blended with omega), as Section IV-C compares them: rounds D-R rounds of
-    the workload's Local-Solver steps (the paper reports 25), SNR and SSIM of
+    blended with omega), as Section IV compares them, then over the block
+    overlap at the proposed method's best lambda (the paper's SNR/SSIM vs
+    overlap plots).  Each solve runs D-R rounds of 10 Local-Solver steps
+    until the residual reaches 1e-4 (at most 400 rounds); SNR and SSIM of
     the observed crop of x_hat against the scene."""
     import torch
     from paper_1705_06603_amd import _lib as dl
-    from paper_1705_06603_amd import quality
-    r = w.r
-    truth = scene[r:r + w.M, r:r + w.M]
+    from paper_1705_06603_amd import quality, workloads
+    q = QUALITY
+    M, r = q["M"], q["psf"] // 2
+    scene = workloads.dead_leaves((M + 2 * r, M + 2 * r), q["seed"])
+    psfs = workloads.gaussian_psf_grid_radial(q["grid"], q["psf"])
+
+    def params(lam, independent, overlap=q["overlap"]):
+        p = dl.make_params(M, q["tiles"], q["pitch"], overlap, q["grid"], q["psf"], reg=dl.REG_HUBER,
+                           bc=dl.BC_CIRCULAR, lam=lam, reg_param=q["delta"], gamma=q["gamma"],
+                           independent=independent)
+        if overlap == q["overlap"]:
+            p.fft_size = plan.frame
+        return p
+
+    c = dl.Context(params(1e-3, False), psfs)
+    blurred = c.blur_global(torch.tensor(scene.astype(np.float32), device="cuda")).cpu().numpy()
+    c.close()
+    y, W = workloads.observe(blurred.astype(np.float64), "gaussian", q["seed"], sigma=q["sigma"])
+    truth = scene[r:r + M, r:r + M]
     yd = torch.tensor(y.astype(np.float32), device="cuda")
     Wd = torch.tensor(W.astype(np.float32), device="cuda")
-    out = {"rounds": rounds, "n_inner": w.n_inner, "metric_region": "observed crop, against the scene",
-           "observed": {"snr_db": round(quality.snr_db(y, truth), 4), "ssim": round(quality.ssim(y, truth), 4)},
-           "lambda": list(lams), "proposed": [], "independent": []}
-    for lam in lams:
-        for label, ind in (("proposed", False), ("independent", True)):
-            params = dl.make_params(w.M, w.tiles, w.pitch, w.overlap, w.grid, w.psf_size, lam=lam,
-                                    reg_param=w.eps, gamma=w.gamma, rho=w.rho, independent=ind)
-            params.fft_size = plan.frame
-            c = dl.Context(params, psfs)
+
+    def solve(lam, independent, overlap=q["overlap"]):
+        c = dl.Context(params(lam, independent, overlap), psfs)
+        if overlap == q["overlap"]:
             c.set_plan(plan)
-            c.set_observation(yd, Wd)
-            c.init()
-            c.run(rounds, w.n_inner)
-            xh = c.assemble().cpu().numpy()[r:r + w.M, r:r + w.M]
-            c.close()
-            out[label].append({"snr_db": round(quality.snr_db(xh, truth), 4),
-                               "ssim": round(quality.ssim(xh, truth), 4)})
+        c.set_observation(yd, Wd)
+        c.init()
+        res = []
+        while len(res) < q["max_rounds"]:
+            res += c.run(min(100, q["max_rounds"] - len(res)), 10, tol=q["tol"])
+            if res[-1] <= q["tol"]:
+                break
+        xh = c.assemble().cpu().numpy()[r:r + M, r:r + M]
+        c.close()
+        return {"snr_db": round(quality.snr_db(xh, truth), 4), "ssim": round(quality.ssim(xh, truth), 4),
+                "rounds": len(res), "residual": res[-1]}
+
+    out = {"scene": "dead leaves (r^-3 disk radii 2-160 px, grey levels U(0.05, 1)), seed %d" % q["seed"],
+           "psfs": "8 x 8 elliptical Gaussians 31 x 31, FWHM 3.5 -> 8.5 x 6.5 px radially",
+           "noise": "Gaussian, sigma = 1/300 of the peak (variance 400 at 6000 photons), W = 1",
+           "prior": "Huber, delta = 1/60 of the peak (100 photons), circular differences",
+           "stop": "residual <= %g or %d D-R rounds of 10 steps" % (q["tol"], q["max_rounds"]),
+           "metric_region": "observed crop, against the scene",
+           "observed": {"snr_db": round(quality.snr_db(y, truth), 4), "ssim": round(quality.ssim(y, truth), 4)},
+           "lambda_paper_units": list(lams_paper), "lambda": [400.0 * l for l in lams_paper],
+           "proposed": [], "independent": []}
+    for lp in lams_paper:
+        for label, ind in (("proposed", False), ("independent", True)):
+            out[label].append(solve(400.0 * lp, ind))
+    for label in ("proposed", "independent"):
+        b = max(range(len(lams_paper)), key=lambda i: out[label][i]["snr_db"])
+        out["best_" + label] = dict(out[label][b], lambda_paper_units=lams_paper[b])
+    lp = out["best_proposed"]["lambda_paper_units"]
+    out["overlap_sweep"] = {"lambda_paper_units": lp, "overlap": list(overlaps),
+                            "proposed": [solve(400.0 * lp, False, o) for o in overlaps],
+                            "independent": [solve(400.0 * lp, True, o) for o in overlaps]}
     print("# quality sweep done", file=sys.stderr, flush=True)
     return out
 
@@ -543,7 +593,7 @@ def convergence(args):
     net.close()
     fctx.close()
     vctx.close()
-    out["quality_sweep"] = quality_sweep(w, scene, psfs, y, W, ctx.plan())
+    out["quality_sweep"] = quality_sweep(ctx.plan())
     ctx.close()
     return out
 

@@ -28,7 +28,9 @@ __all__ = [
     "Workload",
     "WORKLOADS",
     "star_field",
+    "dead_leaves",
     "gaussian_psf_grid",
+    "gaussian_psf_grid_radial",
     "moffat_psf_grid",
     "observe",
     "make_workload",
@@ -124,6 +126,44 @@ def star_field(shape, seed, *, stars_per_256sq=50.0, blobs_per_256sq=3.0,
     return img
 
 
+def dead_leaves(shape, seed, *, r_min=2.0, r_max=160.0, coverage=6.0, level_lo=0.05, level_hi=1.0):
+    """Natural-image stand-in: the dead-leaves model (occluding opaque disks).
+
+    Disk radii follow the scale-invariant density p(r) ~ r^-3 on
+    [r_min, r_max] (inverse-CDF sampling), centres are uniform, grey levels
+    uniform on [level_lo, level_hi]; disks are painted in draw order, later
+    ones on top; their summed area is ``coverage`` times the area their
+    centres are drawn from (the image grown by r_max on every side), and
+    uncovered pixels keep level_lo.  Such images have the
+    edge-and-flat-region structure and the power-law spectrum of natural
+    photographs.  Returns a float64 array of ``shape``.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ny, nx = shape
+    img = np.full((ny, nx), level_lo, dtype=np.float64)
+    # mean disk area under p(r) ~ r^-3: pi r_min^2 r_max^2 ln(r_max/r_min) * 2 / (r_max^2 - r_min^2)
+    a2, b2 = r_min * r_min, r_max * r_max
+    mean_area = 2.0 * math.pi * a2 * b2 * math.log(r_max / r_min) / (b2 - a2)
+    # centres fall on the image grown by r_max on every side
+    n = int(math.ceil(coverage * (ny + 2 * r_max) * (nx + 2 * r_max) / mean_area))
+    u = rng.random(n)
+    # inverse CDF of p(r) ~ r^-3 on [a, b]: r = (1/a^2 - u (1/a^2 - 1/b^2))^(-1/2)
+    rad = (1.0 / a2 - u * (1.0 / a2 - 1.0 / b2)) ** -0.5
+    cy = rng.uniform(-r_max, ny + r_max, size=n)
+    cx = rng.uniform(-r_max, nx + r_max, size=n)
+    lev = rng.uniform(level_lo, level_hi, size=n)
+    for r0, y0, x0, v in zip(rad, cy, cx, lev):
+        y_lo, y_hi = max(0, int(math.floor(y0 - r0))), min(ny, int(math.ceil(y0 + r0)) + 1)
+        x_lo, x_hi = max(0, int(math.floor(x0 - r0))), min(nx, int(math.ceil(x0 + r0)) + 1)
+        if y_lo >= y_hi or x_lo >= x_hi:
+            continue
+        yy = np.arange(y_lo, y_hi)[:, None] - y0
+        xx = np.arange(x_lo, x_hi)[None, :] - x0
+        m = yy * yy + xx * xx <= r0 * r0
+        img[y_lo:y_hi, x_lo:x_hi][m] = v
+    return img
+
+
 def _normalise(h):
     h = np.maximum(h, 0.0)
     return h / h.sum()
@@ -145,6 +185,34 @@ def gaussian_psf_grid(grid, size, sigma_lo=1.5, sigma_hi=3.0):
             t = 0.0 if grid == 1 else (a + b) / (2.0 * (grid - 1))
             s = sigma_lo + (sigma_hi - sigma_lo) * t
             out[a, b] = _normalise(np.exp(-(yy * yy + xx * xx) / (2 * s * s)))
+    return out
+
+
+def gaussian_psf_grid_radial(grid, size, fwhm_centre=3.5, fwhm_corner=(8.5, 6.5)):
+    """grid x grid elliptical Gaussian PSFs, size x size, unit sum, in the
+    manner of the smooth shift-variant experiments of Section IV: FWHM
+    ``fwhm_centre`` at the field centre growing linearly with the node's
+    normalised radius rho_n to ``fwhm_corner`` (major, minor) at the
+    corners, major axis radial.  Returns float64 [grid, grid, size, size].
+    """
+    r = size // 2
+    q = np.arange(-r, r + 1, dtype=np.float64)
+    yy, xx = np.meshgrid(q, q, indexing="ij")
+    c = (grid - 1) / 2.0
+    rmax = max(math.hypot(c, c), 1e-12)
+    f2s = 1.0 / (2.0 * math.sqrt(2.0 * math.log(2.0)))   # FWHM -> sigma
+    out = np.empty((grid, grid, size, size))
+    for a in range(grid):
+        for b in range(grid):
+            dy, dx = a - c, b - c
+            rho = math.hypot(dy, dx) / rmax if grid > 1 else 0.0
+            s_major = (fwhm_centre + (fwhm_corner[0] - fwhm_centre) * rho) * f2s
+            s_minor = (fwhm_centre + (fwhm_corner[1] - fwhm_centre) * rho) * f2s
+            theta = math.atan2(dy, dx) if rho > 0 else 0.0
+            ct, st = math.cos(theta), math.sin(theta)
+            u = xx * ct + yy * st
+            v = -xx * st + yy * ct
+            out[a, b] = _normalise(np.exp(-0.5 * ((u / s_major) ** 2 + (v / s_minor) ** 2)))
     return out
 
 
