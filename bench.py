@@ -705,6 +705,13 @@ def main():
                                     "traffic": counters[KERNELS_PER_STEP.index(dom)]},
                 "all_kernels_ms": {k: round(v, 5) for k, v in kms.items()},
                 "all_kernels_design_GBps": {k: round(kb[k] / (kms[k] * 1e-3) / 1e9, 1) for k in kms}}
+    if traffic is not None:
+        # the HBM bytes the counters saw, over the same kernel time: how busy
+        # HBM is, beside the algorithmic rate above
+        roofline["traffic_GBps"] = round(traffic / (step_ms * 1e-3) / 1e9, 1)
+        roofline["traffic_frac"] = round(traffic / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        roofline["all_kernels_traffic_GBps"] = {k: round(c / (kms[k] * 1e-3) / 1e9, 1)
+                                                for k, c in zip(KERNELS_PER_STEP, counters)}
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": UNIT, "n_gpus": 1, "steps": args.steps,
