@@ -1023,18 +1023,24 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
 
     // ---- phase 3: forward row spectra of b_k . x_new (x_new re-read from
     // the frame just written, an L2 hit, rather than held in registers)
-    const float* xw = xn + (size_t)t * N * N + (size_t)i0 * N;
+    // the wave's rows of the new x are read once (an L2 hit) and kept in
+    // registers for every k_x
+    float2 xr[kV];
+    {
+        const float* xw = xn + (size_t)t * N * N + (size_t)i0 * N;
+        const float* __restrict__ xl = xw + wave * C::LwR * N + rslot_base<N>(fresh_lane(lane));
+#pragma unroll
+        for (int s = 0; s < kV; ++s) xr[s] = *reinterpret_cast<const float2*>(xl + rslot_off<N>(s));
+    }
     for (int kx = 0; kx < ti.nkx; ++kx) {
         const float* bm = tentX + ((size_t)ti.tx * kMaxK + kx) * N;
         float2 v[kV];
         const int ln = fresh_lane(lane);
         const float* __restrict__ bl = bm + rslot_tent<N>(ln);
-        const float* __restrict__ xl = xw + wave * C::LwR * N + rslot_base<N>(ln);
 #pragma unroll
         for (int s = 0; s < kV; ++s) {
             const float2 b = *reinterpret_cast<const float2*>(bl + rslot_off<N>(s));
-            const float2 xv = *reinterpret_cast<const float2*>(xl + rslot_off<N>(s));
-            v[s] = make_float2(b.x * xv.x, b.y * xv.y);
+            v[s] = make_float2(b.x * xr[s].x, b.y * xr[s].y);
         }
         __syncthreads();
         row_fft_wave<N>(v, sw, tw, lane);
