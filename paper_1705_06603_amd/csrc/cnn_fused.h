@@ -32,22 +32,41 @@ static_assert(kR2 == 32, "a2 rows must be two 16-pixel chunks");
 static_assert(kR3 * kR3 * C <= kBufA, "a3 must fit where a1 was");
 static_assert(kR0 * kR0 * 2 <= kBufB, "the x staging must fit in buffer B");
 
-// One 16-pixel x 32-channel output chunk of a 32 -> 32 layer from the LDS
-// region `src` (row stride sw pixels): output pixel (r, c0 + l) reads input
-// (r + dy, c0 + l + dx) for tap (dy, dx).  Lanes whose column would pass
-// the region's last valid input column read a clamped column (their output
-// is discarded).
-__device__ __forceinline__ void mid_chunk(const unsigned short* __restrict__ src, int sw, int r, int c0, int cmax,
-                                          const uint4 (&bw0)[9], const uint4 (&bw1)[9], int li, int lk, f32x4& acc0,
-                                          f32x4& acc1) {
+// A operands of one input row for the three horizontal taps of a 16-pixel
+// output chunk (output pixel c0 + l reads input columns c0 + l + dx): each
+// lane reads its centre column c0 + l + 1 from LDS, the taps dx = 0 and 2 are
+// that fragment shifted by one lane inside each 16-lane row (DPP), and the
+// edge lanes (l = 0 for dx = 0, l = 15 for dx = 2) read their own column.
+// Columns past the region's last one are clamped into it: only lanes whose
+// output is discarded read them.
+struct RowOps {
+    uint4 a[3];
+};
+
+__device__ __forceinline__ RowOps row_ops(const unsigned short* __restrict__ rowp, int cc, int ce, int li) {
+    RowOps o;
+    const uint4 cen = *reinterpret_cast<const uint4*>(rowp + cc * C);
+    uint4 edg = make_uint4(0, 0, 0, 0);
+    if (li == 0 || li == 15) edg = *reinterpret_cast<const uint4*>(rowp + ce * C);
+    const uint4 sl = dpp_row_shift(cen, true);    // lane l gets lane l - 1
+    const uint4 sr = dpp_row_shift(cen, false);   // lane l gets lane l + 1
+    o.a[0] = li == 0 ? edg : sl;
+    o.a[1] = cen;
+    o.a[2] = li == 15 ? edg : sr;
+    return o;
+}
+
+// One 16-pixel x 32-channel output chunk from the operands of its three input
+// rows, taps in the order t = 3 dy + dx (the order of the layer-by-layer
+// kernel, so the sums round identically).
+__device__ __forceinline__ void mid_chunk(const RowOps& r0, const RowOps& r1, const RowOps& r2,
+                                          const uint4 (&bw0)[9], const uint4 (&bw1)[9], f32x4& acc0, f32x4& acc1) {
     acc0 = f32x4{0.f, 0.f, 0.f, 0.f};
     acc1 = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int col = min(c0 + li, cmax);
+    const RowOps* rows[3] = {&r0, &r1, &r2};
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-        const int dy = t / 3, dx = t % 3;
-        const uint4 a = *reinterpret_cast<const uint4*>(src + ((r + dy) * sw + col + dx) * C + 8 * lk);
-        const bf16x8 Aop = __builtin_bit_cast(bf16x8, a);
+        const bf16x8 Aop = __builtin_bit_cast(bf16x8, rows[t / 3]->a[t % 3]);
         acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop, __builtin_bit_cast(bf16x8, bw0[t]), acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aop, __builtin_bit_cast(bf16x8, bw1[t]), acc1, 0, 0, 0);
     }
@@ -127,19 +146,39 @@ __global__ __launch_bounds__(kFusedThreads) void k_cnn_fwd(const float* __restri
         const int sw = layer == 0 ? kR1 : kR2;        // input region side
         const int side = layer == 0 ? kR2 : kR3;      // output region side
         const int off = layer == 0 ? 2 : 1;           // output region origin: (Y0 - off, X0 - off)
-        for (int u = wave; u < side * 2; u += kFusedThreads / 64) {
-            const int r = u >> 1, c0 = 16 * (u & 1);
+        // wave w: column chunk c0 = 16 (w mod 2) of the output rows of band
+        // w / 2 (a quarter of the rows), walked top to bottom with the operands
+        // of the three input rows a chunk needs kept in registers, so each
+        // input row is read from LDS once per wave
+        const int c0 = 16 * (wave & 1), band = wave >> 1;
+        const int r_lo = band * side / 4, r_hi = (band + 1) * side / 4;
+        const int cc = min(c0 + li + 1, sw - 1);
+        const int ce = li == 0 ? c0 : min(c0 + 17, sw - 1);
+        const unsigned short* rows = src + 8 * lk;
+        auto chunk = [&](int r, const RowOps& q0, const RowOps& q1, const RowOps& q2) {
             f32x4 acc0, acc1;
-            mid_chunk(src, sw, r, c0, side - 1, bw0, bw1, li, lk, acc0, acc1);
+            mid_chunk(q0, q1, q2, bw0, bw1, acc0, acc1);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int cc = c0 + 4 * lk + q;
-                if (cc >= side) continue;
+                const int cx = c0 + 4 * lk + q;
+                if (cx >= side) continue;
                 float v0 = fmaxf(acc0[q] + b0v, 0.f), v1 = fmaxf(acc1[q] + b1v, 0.f);
-                if (!inside(d, Y0 - off + r, X0 - off + cc)) v0 = v1 = 0.f;
-                dst[(r * side + cc) * C + li] = f2bf(v0);
-                dst[(r * side + cc) * C + 16 + li] = f2bf(v1);
+                if (!inside(d, Y0 - off + r, X0 - off + cx)) v0 = v1 = 0.f;
+                dst[(r * side + cx) * C + li] = f2bf(v0);
+                dst[(r * side + cx) * C + 16 + li] = f2bf(v1);
             }
+        };
+        RowOps A = row_ops(rows + (size_t)r_lo * sw * C, cc, ce, li);
+        RowOps B = row_ops(rows + (size_t)(r_lo + 1) * sw * C, cc, ce, li);
+        for (int r = r_lo; r < r_hi; r += 3) {
+            RowOps Cn = row_ops(rows + (size_t)(r + 2) * sw * C, cc, ce, li);
+            chunk(r, A, B, Cn);
+            if (r + 1 >= r_hi) break;
+            A = row_ops(rows + (size_t)(r + 3) * sw * C, cc, ce, li);
+            chunk(r + 1, B, Cn, A);
+            if (r + 2 >= r_hi) break;
+            B = row_ops(rows + (size_t)(r + 4) * sw * C, cc, ce, li);
+            chunk(r + 2, Cn, A, B);
         }
         __syncthreads();
     }
