@@ -183,6 +183,7 @@ template <> struct XPad<320, kInv, 0> { static constexpr int B = 16, P = 1; };
 template <> struct XPad<640, kFwd, 0> { static constexpr int B = 160, P = 1; };
 template <> struct XPad<640, kFwd, 1> { static constexpr int B = 160, P = 4; };
 template <> struct XPad<640, kInv, 0> { static constexpr int B = 16, P = 1; };
+template <> struct XPad<640, kInv, 1> { static constexpr int B = 32, P = 2; };
 template <> struct XPad<160, kFwd, 0> { static constexpr int B = 40, P = 1; };
 template <> struct XPad<160, kFwd, 1> { static constexpr int B = 80, P = 4; };
 
