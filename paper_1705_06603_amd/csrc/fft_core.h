@@ -270,6 +270,9 @@ __device__ __forceinline__ void slot_pos(int lane, int s, int& line, int& elem) 
 // across the callers' loops, which would cost registers per slot and pass.
 __device__ __forceinline__ int fresh_lane(int lane) {
     asm volatile("" : "+v"(lane));
+    // a lane or thread index: non-negative, so divisions and remainders by
+    // constants need no sign fix-ups
+    __builtin_assume(lane >= 0);
     return lane;
 }
 
