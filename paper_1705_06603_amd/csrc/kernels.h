@@ -766,9 +766,10 @@ constexpr int kSeg = 8;
 //          columns of a strip and takes horizontal neighbours from adjacent
 //          lanes (one regulariser scale per pixel); with circular
 //          differences a thread owns one column and loads x at c - 1, c and
-//          c + 1.  Writes the new x frame.
-// Phase 3: each wave re-reads its rows of the new x (an L2 hit) and, per mask
-//          k, does the forward row FFT and the transposed store of Z_k.
+//          c + 1.  Writes the new x frame, and the new value of each pixel
+//          over its gradient in LDS.
+// Phase 3: each wave reads its rows of the new x from LDS and, per mask k,
+//          does the forward row FFT and the transposed store of Z_k.
 //
 // FISTA (accelerated Local-Solver): xc holds the gradient point y_j, the
 // projected step gives w_j, which is stored in wb, and the next gradient
@@ -876,6 +877,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                 // pixel (ia, c) in the frame and in sg; row ia + k at offset k N
                 const size_t o = (size_t)ia * N + c;
                 const float* sgs = sg + (ia - i0) * N + c;
+                float* sgw = sg + (ia - i0) * N + c;   // the same pixel: its new value
                 float* __restrict__ xos = xo + o;
                 const bool colin = c >= 0 && c < sx;
                 const bool rin = c + 1 < sx;   // the right neighbour is in the support
@@ -912,12 +914,13 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                     }
                     qv_up = qv;
                     if (lane >= 1 && lane <= OWN && c < N) {
+                        float xv = val;
                         if constexpr (FISTA) {
                             wt[o + (size_t)k * N] = val;
-                            xos[k * N] = beta != 0.f ? val + beta * (val - U[kSeg + k]) : val;
-                        } else {
-                            xos[k * N] = val;
+                            if (beta != 0.f) xv = val + beta * (val - U[kSeg + k]);
                         }
+                        xos[k * N] = xv;
+                        sgw[k * N] = xv;
                     }
                 }
             };
@@ -1008,27 +1011,27 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                         val = xm - tt * grad;
                         if (P.positivity) val = project_nonneg(val);
                     }
+                    float xv = val;
                     if constexpr (FISTA) {
                         const float wp = wt[(size_t)i * N + c];   // 0 outside the support
                         wt[(size_t)i * N + c] = val;
-                        xo[(size_t)i * N + c] = beta != 0.f ? val + beta * (val - wp) : val;
-                    } else {
-                        xo[(size_t)i * N + c] = val;
+                        if (beta != 0.f) xv = val + beta * (val - wp);
                     }
+                    xo[(size_t)i * N + c] = xv;
+                    sg[(i - i0) * N + c] = xv;
                 }
             }
         }
         __syncthreads();
     }
 
-    // ---- phase 3: forward row spectra of b_k . x_new (x_new re-read from
-    // the frame just written, an L2 hit, rather than held in registers)
-    // the wave's rows of the new x are read once (an L2 hit) and kept in
-    // registers for every k_x
+    // ---- phase 3: forward row spectra of b_k . x_new.  Phase 2 left x_new
+    // in the LDS frame (each pixel's gradient replaced by its new value);
+    // the wave's rows are read from there once and kept in registers for
+    // every k_x.
     float2 xr[kV];
     {
-        const float* xw = xn + (size_t)t * N * N + (size_t)i0 * N;
-        const float* __restrict__ xl = xw + wave * C::LwR * N + rslot_base<N>(fresh_lane(lane));
+        const float* __restrict__ xl = sg + wave * C::LwR * N + rslot_base<N>(fresh_lane(lane));
 #pragma unroll
         for (int s = 0; s < kV; ++s) xr[s] = *reinterpret_cast<const float2*>(xl + rslot_off<N>(s));
     }
