@@ -881,6 +881,10 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                 float* __restrict__ xos = xo + o;
                 const bool colin = c >= 0 && c < sx;
                 const bool rin = c + 1 < sx;   // the right neighbour is in the support
+                // lanes 1..OWN own their column; the halo lanes only supply
+                // neighbour values and never touch the LDS frame, whose
+                // pixels their neighbouring tasks overwrite
+                const bool own = lane >= 1 && lane <= OWN && c < N;
                 // vertical flux of the row above the strip
                 float qv_up = 0.f;
                 {
@@ -904,7 +908,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                     const float qh = sc * gh, qv = sc * gv;
                     const float qh_l = from_prev_lane(qh);
                     float val = 0.f;
-                    if (pin) {
+                    if (pin && own) {
                         // -div of the flux (s gh, s gv): backward differences
                         const float g = (qh_l - qh) + (qv_up - qv);
                         const float alpha = P.gamma * oy[i] * oxc;
@@ -913,7 +917,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                         if (P.positivity) val = project_nonneg(val);
                     }
                     qv_up = qv;
-                    if (lane >= 1 && lane <= OWN && c < N) {
+                    if (own) {
                         float xv = val;
                         if constexpr (FISTA) {
                             wt[o + (size_t)k * N] = val;
