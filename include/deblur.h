@@ -352,9 +352,10 @@ int deblur_get_plan(const deblur_ctx* ctx, deblur_plan* plan_host);
 
 /* Replaces the context's plan (host in).  plan.frame must equal the
  * context's frame (0 is taken as that frame); waves, order and tile_groups
- * must be among the values above, else DEBLUR_E_ARG.  Synchronises the context stream and
- * drops the captured graphs of deblur_run, which are re-captured with the
- * new shapes on their next use.  State and observation are kept. */
+ * must be among the values above, else DEBLUR_E_ARG.  Synchronises the
+ * context's streams.  The graphs deblur_run captures are kept per plan until
+ * deblur_destroy: the new plan's rounds are captured on their first use and
+ * reused when the plan is set again.  State and observation are kept. */
 int deblur_set_plan(deblur_ctx* ctx, const deblur_plan* plan_host);
 
 /* Autotuner.  For the problem (params, psfs_host as for deblur_create) it

@@ -225,7 +225,9 @@ struct deblur_ctx {
     int vm_gc = 0, vm_rc = 0;     // current gradient / residual buffer
     int max_cover = 2;            // the most tiles covering an X row or column
     std::vector<void*> allocs;
-    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;   // (steps, parity, with consensus)
+    // captured rounds, keyed by (col waves, row waves, tile order, tile
+    // groups, steps, parity, with consensus); kept until deblur_destroy
+    std::map<std::tuple<int, int, int, int, int, int, int>, hipGraphExec_t> graphs;
     std::vector<hipGraph_t> graph_defs;
     // launch plan (frame fixed at creation; the rest set by deblur_set_plan)
     deblur_plan plan{};
@@ -1021,9 +1023,14 @@ int compute_rowsums(deblur_ctx* c) {
 }
 
 // The captured graph of n_inner Local-Solver steps from x[parity], followed
-// by the consensus step when with_consensus (one D-R round); cached per key.
+// by the consensus step when with_consensus (one D-R round), under the
+// current launch plan; cached per plan and key for the context's lifetime,
+// so a change of plan captures the new plan's rounds (once) and leaves the
+// earlier ones in place.
 int ensure_graph(deblur_ctx* c, int n_inner, int parity, bool with_consensus, hipGraphExec_t* out) {
-    const auto key = std::make_tuple(n_inner, parity, with_consensus ? 1 : 0);
+    const deblur_plan& pl = c->plan;
+    const auto key = std::make_tuple(pl.col_waves, pl.row_waves, pl.tile_order, pl.tile_groups, n_inner, parity,
+                                     with_consensus ? 1 : 0);
     auto it = c->graphs.find(key);
     if (it != c->graphs.end()) {
         *out = it->second;
@@ -1570,7 +1577,6 @@ int deblur_set_plan(deblur_ctx* c, const deblur_plan* pl) {
         return fail(c, DEBLUR_E_ARG, "tile_groups must be 1, 2 or 4");
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     for (hipStream_t a : c->aux_stream) HIP_TRY(c, hipStreamSynchronize(a));
-    drop_graphs(c);
     c->plan = *pl;
     c->plan.frame = c->N;
     HIP_TRY(c, preload_plan(c));
