@@ -61,8 +61,8 @@ WORKLOAD_TEXT = {
              "PSFs with field-dependent FWHM and rotation, Poisson+read noise, smoothed TV + positivity, 300 "
              "iterations (30 D-R rounds x 10 Local-Solver steps), plain start, one solve per step",
     "combined": "combined: 16384x16384 image, 32x32 tiles of 512 px + 64-px overlap, 32x32 grid of 63x63 Moffat "
-                "PSFs, Poisson+read noise, smoothed TV + positivity; CNN warm start on all 1024 tiles (one "
-                "launch per layer) with per-tile fallback, then 200 iterations (20 D-R rounds x 10 "
+                "PSFs, Poisson+read noise, smoothed TV + positivity; CNN warm start on all 1024 tiles (all "
+                "four layers in one fused launch) with per-tile fallback, then 200 iterations (20 D-R rounds x 10 "
                 "Local-Solver steps), one warm-started solve per step",
 }
 
