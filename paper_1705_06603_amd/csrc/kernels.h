@@ -854,22 +854,32 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                 const int c = (task % NCG) * OWN - 1 + lane;
                 const int ia = i0 + (task / NCG) * kSeg;
                 const bool colin = c >= 0 && c < sx;
-                // column c from row ia: row ia + j at a compile-time offset j N
-                const size_t o = (size_t)ia * N + c;
+                // Every load is unconditional, from the column and the halo
+                // rows clamped into the frame, and a value outside the
+                // support is replaced by 0 afterwards (no exec-mask branch
+                // per load).  Rows ia .. ia + kSeg - 1 lie in the frame.
+                const int cc = min(max(c, 0), N - 1);
+                const size_t o = (size_t)ia * N + cc;
                 const float* __restrict__ xs = xt + o;
                 const float* __restrict__ us = ut + o;
+                X[0] = xt[(size_t)max(ia - 1, 0) * N + cc];
 #pragma unroll
-                for (int j = 0; j < kSeg + 2; ++j) {
-                    const int rr = ia - 1 + j;
-                    X[j] = (colin && rr >= 0 && rr < sy) ? xs[(j - 1) * N] : 0.f;
-                }
+                for (int j = 1; j <= kSeg; ++j) X[j] = xs[(j - 1) * N];
+                X[kSeg + 1] = xt[(size_t)min(ia + kSeg, N - 1) * N + cc];
 #pragma unroll
-                for (int k = 0; k < kSeg; ++k) U[k] = (colin && ia + k < sy) ? us[k * N] : 0.f;
+                for (int k = 0; k < kSeg; ++k) U[k] = us[k * N];
                 if constexpr (FISTA) {
                     const float* __restrict__ ws = wt + o;
 #pragma unroll
-                    for (int k = 0; k < kSeg; ++k) U[kSeg + k] = (colin && ia + k < sy) ? ws[k * N] : 0.f;
+                    for (int k = 0; k < kSeg; ++k) U[kSeg + k] = ws[k * N];
                 }
+#pragma unroll
+                for (int j = 0; j < kSeg + 2; ++j) {
+                    const int rr = ia - 1 + j;
+                    X[j] = (colin && rr >= 0 && rr < sy) ? X[j] : 0.f;
+                }
+#pragma unroll
+                for (int k = 0; k < UN; ++k) U[k] = (colin && ia + k % kSeg < sy) ? U[k] : 0.f;
             };
             auto update = [&](int task, const float (&X)[kSeg + 2], const float (&U)[UN]) {
                 const int c = (task % NCG) * OWN - 1 + lane;
