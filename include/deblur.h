@@ -141,7 +141,8 @@ typedef struct deblur_params {
     int32_t positivity;   /* 1: x >= 0 constraint of Eq. (3), 0: none     */
     int32_t fft_size;     /* 0: chosen by the library; else 160/320/640   */
     float lambda;         /* regularisation weight                        */
-    float reg_param;      /* eps (smoothed TV) or delta (Huber), > 0      */
+    float reg_param;      /* eps (smoothed TV, >= 2^-63 so that eps^2 is a
+                             normal float) or delta (Huber), > 0          */
     float gamma;          /* metric alpha_t = gamma * omega_t, > 0        */
     float rho;            /* D-R relaxation, in (0, 2)                    */
     int32_t local_solver; /* DEBLUR_SOLVER_*                              */

@@ -1132,6 +1132,8 @@ int deblur_create(const deblur_params* params, const float* psfs_host, void* str
     if (p.bc != DEBLUR_BC_NEUMANN && p.bc != DEBLUR_BC_CIRCULAR) return fail(nullptr, DEBLUR_E_ARG, "bc");
     if (!(p.reg_param > 0.f) || !(p.gamma > 0.f) || !(p.lambda >= 0.f) || !(p.rho > 0.f && p.rho < 2.f))
         return fail(nullptr, DEBLUR_E_ARG, "need reg_param > 0, gamma > 0, lambda >= 0, 0 < rho < 2");
+    if (p.reg == DEBLUR_REG_SMOOTH_TV && !(p.reg_param >= 0x1p-63f))   // eps^2 a normal float
+        return fail(nullptr, DEBLUR_E_ARG, "smoothed TV needs eps >= 2^-63 (eps^2 must be a normal float)");
     if (p.local_solver != DEBLUR_SOLVER_PG && p.local_solver != DEBLUR_SOLVER_FISTA &&
         p.local_solver != DEBLUR_SOLVER_VMLMB)
         return fail(nullptr, DEBLUR_E_ARG, "local_solver");

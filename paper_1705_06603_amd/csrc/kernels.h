@@ -735,11 +735,21 @@ __device__ __forceinline__ float project_nonneg(float v) { return v < 0.f ? 0.f 
 // Scale of the regulariser's derivative for a forward-difference vector g:
 // d phi / d g = s(g) g with s = 1/sqrt(|g|^2 + eps^2) (smoothed TV) or
 // delta / max(|g|, delta) (Huber).
-__device__ __forceinline__ float reg_scale(float gh, float gv, const SolveParams& P) {
+// REG is the regulariser kind (0: smoothed TV, 1: Huber) and rp its eps or
+// delta.  For smoothed TV the argument of the reciprocal square root is at
+// least eps^2, a normal number (eps >= 2^-63 is required at creation), where
+// the hardware's reciprocal square root equals rsqrtf (whose extra steps
+// only rescale subnormal arguments).
+template <int REG>
+__device__ __forceinline__ float reg_scale_k(float gh, float gv, float rp) {
     const float n2 = gh * gh + gv * gv;
-    if (P.reg == 0) return rsqrtf(n2 + P.reg_param * P.reg_param);
-    return P.reg_param * __frcp_rn(fmaxf(sqrtf(n2), P.reg_param));
+    if constexpr (REG == 0) return __builtin_amdgcn_rsqf(n2 + rp * rp);
+    else return rp * __frcp_rn(fmaxf(sqrtf(n2), rp));
 }
+__device__ __forceinline__ float reg_scale(float gh, float gv, const SolveParams& P) {
+    return P.reg == 0 ? reg_scale_k<0>(gh, gv, P.reg_param) : reg_scale_k<1>(gh, gv, P.reg_param);
+}
+template <int V> struct IntC { static constexpr int value = V; };
 
 // Value of v in the next (lane + 1) and previous (lane - 1) lane of the wave,
 // by a whole-wave DPP shift (a VALU operation, no LDS traffic); lane 63
@@ -754,6 +764,7 @@ __device__ __forceinline__ float from_prev_lane(float v) {
 // Tasks of the column-strip update phase: every column split into segments
 // of kSeg rows, (N / RB-row workgroup) -> N * RB / kSeg tasks, a multiple of NT.
 constexpr int kSeg = 8;
+static_assert((kSeg & (kSeg - 1)) == 0, "the strip rows are picked by lane mod kSeg");
 
 // H^T r (from Gk), regulariser and metric terms, projected step; then the
 // masked row spectra of the new iterate for the next step.
@@ -790,7 +801,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
     __shared__ float2 tw[C::TWR];
     float* sg = reinterpret_cast<float*>(sbuf);   // [RB][N] natural view
     const int t = t0 + blockIdx.y, i0 = blockIdx.x * C::RB;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     load_twiddles<N, WV, false>(tw, twg, tid);
     const TileInfo ti = tiles[t];
     float2* sw = sbuf + line_off<C::n>(wave * C::LwR);
@@ -850,14 +861,18 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
             constexpr int NTASK = NCG * SEGS;
             // U holds u on the task's rows, then (FISTA) the previous w_{j-1}
             constexpr int UN = FISTA ? 2 * kSeg : kSeg;
-            auto load = [&](int task, float (&X)[kSeg + 2], float (&U)[UN]) {
+            // O[0] = omega_x of the lane's column, O[1] = omega_y of the
+            // strip's row ia + (lane mod kSeg), read per row by readlane: the
+            // update issues no global load of its own, so its waits never
+            // reach the later strips' loads (the load counter drains in order)
+            auto load = [&](int task, float (&X)[kSeg + 2], float (&U)[UN], float (&O)[2]) {
                 const int c = (task % NCG) * OWN - 1 + lane;
                 const int ia = i0 + (task / NCG) * kSeg;
-                const bool colin = c >= 0 && c < sx;
                 // Every load is unconditional, from the column and the halo
-                // rows clamped into the frame, and a value outside the
-                // support is replaced by 0 afterwards (no exec-mask branch
-                // per load).  Rows ia .. ia + kSeg - 1 lie in the frame.
+                // rows clamped into the frame (rows ia .. ia + kSeg - 1 lie
+                // in it); the update replaces a value outside the support by
+                // 0 when it uses it, so no exec-mask branch guards a load and
+                // no wait for these loads is taken before that use.
                 const int cc = min(max(c, 0), N - 1);
                 const size_t o = (size_t)ia * N + cc;
                 const float* __restrict__ xs = xt + o;
@@ -873,17 +888,28 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
 #pragma unroll
                     for (int k = 0; k < kSeg; ++k) U[kSeg + k] = ws[k * N];
                 }
-#pragma unroll
-                for (int j = 0; j < kSeg + 2; ++j) {
-                    const int rr = ia - 1 + j;
-                    X[j] = (colin && rr >= 0 && rr < sy) ? X[j] : 0.f;
-                }
-#pragma unroll
-                for (int k = 0; k < UN; ++k) U[k] = (colin && ia + k % kSeg < sy) ? U[k] : 0.f;
+                O[0] = ox[cc];
+                O[1] = oy[min(ia + (lane & (kSeg - 1)), N - 1)];
             };
-            auto update = [&](int task, const float (&X)[kSeg + 2], const float (&U)[UN]) {
+            // the regulariser kind is a compile-time constant of each strip
+            // loop, so its scale takes no per-pixel branch
+            auto update = [&](auto regc, int task, const float (&XL)[kSeg + 2], const float (&UL)[UN],
+                              const float (&O)[2]) {
+                constexpr int REG = decltype(regc)::value;
                 const int c = (task % NCG) * OWN - 1 + lane;
                 const int ia = i0 + (task / NCG) * kSeg;
+                // the loaded values, 0 outside the support
+                float X[kSeg + 2], U[UN];
+                {
+                    const bool cin = c >= 0 && c < sx;
+#pragma unroll
+                    for (int j = 0; j < kSeg + 2; ++j) {
+                        const int rr = ia - 1 + j;
+                        X[j] = (cin && rr >= 0 && rr < sy) ? XL[j] : 0.f;
+                    }
+#pragma unroll
+                    for (int k = 0; k < UN; ++k) U[k] = (cin && ia + k % kSeg < sy) ? UL[k] : 0.f;
+                }
                 // pixel (ia, c) in the frame and in sg; row ia + k at offset k N
                 const size_t o = (size_t)ia * N + c;
                 const float* sgs = sg + (ia - i0) * N + c;
@@ -902,26 +928,27 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                     if (colin && ia >= 1 && ia < sy) {
                         const float gh = rin ? xr - X[0] : 0.f;
                         const float gv = X[1] - X[0];
-                        qv_up = reg_scale(gh, gv, P) * gv;
+                        qv_up = reg_scale_k<REG>(gh, gv, P.reg_param) * gv;
                     }
                 }
-                const float oxc = colin ? ox[c] : 0.f;
+                const float oxc = colin ? O[0] : 0.f;
 #pragma unroll
                 for (int k = 0; k < kSeg; ++k) {
                     const int i = ia + k;
+                    const float oyi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(O[1]), k));
                     const bool pin = colin && i < sy;
                     const float xm = X[k + 1];
                     const float xr = from_next_lane(xm);
                     const float gh = (pin && rin) ? xr - xm : 0.f;
                     const float gv = (pin && i + 1 < sy) ? X[k + 2] - xm : 0.f;
-                    const float sc = reg_scale(gh, gv, P);
+                    const float sc = reg_scale_k<REG>(gh, gv, P.reg_param);
                     const float qh = sc * gh, qv = sc * gv;
                     const float qh_l = from_prev_lane(qh);
                     float val = 0.f;
                     if (pin && own) {
                         // -div of the flux (s gh, s gv): backward differences
                         const float g = (qh_l - qh) + (qv_up - qv);
-                        const float alpha = P.gamma * oy[i] * oxc;
+                        const float alpha = P.gamma * oyi * oxc;
                         const float grad = sgs[k * N] + P.lambda * g + alpha * (xm - U[k]);
                         val = xm - tt * grad;
                         if (P.positivity) val = project_nonneg(val);
@@ -938,20 +965,32 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
                     }
                 }
             };
-            float XA[kSeg + 2], UA[UN], XB[kSeg + 2], UB[UN], XC[kSeg + 2], UC[UN];
-            constexpr int S = C::W;   // task stride of a wave
-            if (wave < NTASK) load(wave, XA, UA);
-            if (wave + S < NTASK) load(wave + S, XB, UB);
-            for (int task = wave; task < NTASK; task += 3 * S) {
-                if (task + 2 * S < NTASK) load(task + 2 * S, XC, UC);
-                update(task, XA, UA);
-                if (task + S >= NTASK) break;
-                if (task + 3 * S < NTASK) load(task + 3 * S, XA, UA);
-                update(task + S, XB, UB);
-                if (task + 2 * S >= NTASK) break;
-                if (task + 4 * S < NTASK) load(task + 4 * S, XB, UB);
-                update(task + 2 * S, XC, UC);
-            }
+            auto strips = [&](auto regc) {
+                float XA[kSeg + 2], UA[UN], XB[kSeg + 2], UB[UN], XC[kSeg + 2], UC[UN];
+                float OA[2], OB[2], OC[2];
+                constexpr int S = C::W;   // task stride of a wave
+                // loads are issued unconditionally (a task past the last one
+                // reloads the last task's strip, unused), so the load counter
+                // sees the same sequence on every path and each update waits
+                // only for its own strip
+                const auto ld = [&](int task, float (&X)[kSeg + 2], float (&U)[UN], float (&O)[2]) {
+                    load(min(task, NTASK - 1), X, U, O);
+                };
+                ld(wave, XA, UA, OA);
+                ld(wave + S, XB, UB, OB);
+                for (int task = wave; task < NTASK; task += 3 * S) {
+                    ld(task + 2 * S, XC, UC, OC);
+                    update(regc, task, XA, UA, OA);
+                    if (task + S >= NTASK) break;
+                    ld(task + 3 * S, XA, UA, OA);
+                    update(regc, task + S, XB, UB, OB);
+                    if (task + 2 * S >= NTASK) break;
+                    ld(task + 4 * S, XB, UB, OB);
+                    update(regc, task + 2 * S, XC, UC, OC);
+                }
+            };
+            if (P.reg == 0) strips(IntC<0>{});
+            else strips(IntC<1>{});
         } else
         // Circular differences: one thread per (column, kSeg rows), x at
         // c - 1, c, c + 1 loaded per row.  Two tasks per step: their loads

@@ -79,3 +79,20 @@ def test_create_rejects_a_psf_not_summing_to_one():
     psfs[1, 1] *= 1.0 - 2e-4
     rc, msg = _create_error(psfs)
     assert rc == -1 and "node 3" in msg, msg
+
+
+def test_create_rejects_a_smoothing_eps_whose_square_is_subnormal():
+    """Smoothed TV needs eps^2 to be a normal float (eps >= 2^-63): the
+    regulariser's reciprocal square root is then exact hardware rsq."""
+    from paper_1705_06603_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    import numpy as np
+    L = _lib.lib()
+    psf = np.ascontiguousarray(_unit_psfs(), dtype=np.float32)
+    for eps in (1e-20, 2.0 ** -64):
+        params = _lib.make_params(24, 2, 12, 2, 2, 3, reg_param=eps)
+        h = ctypes.c_void_p()
+        rc = L.deblur_create(ctypes.byref(params), psf.ctypes.data_as(ctypes.c_void_p), None, ctypes.byref(h))
+        assert rc == -1 and not h.value
+        assert "2^-63" in L.deblur_last_error(None).decode()
