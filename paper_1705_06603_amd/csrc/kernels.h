@@ -511,7 +511,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_H(const float2* __rest
     constexpr int LPL = lanes_per_line<N>();
     __shared__ float2 lds[C::W * (C::LwC * C::LSC + kLinePad)];
     __shared__ float2 tw[C::TWC];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const ColItem it = col_item<N, WV>(n_tiles, perm, order, wave);
     load_twiddles<N, WV, true>(tw, twg, tid);
     __syncthreads();
@@ -571,7 +571,7 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_Ht(const float2* __res
     constexpr int LPL = lanes_per_line<N>();
     __shared__ float2 lds[C::W * (C::LwC * C::LSC + kLinePad)];
     __shared__ float2 tw[C::TWC];
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const ColItem it = col_item<N, WV>(n_tiles, perm, order, wave);
     load_twiddles<N, WV, true>(tw, twg, tid);
     __syncthreads();
