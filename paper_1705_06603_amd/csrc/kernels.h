@@ -523,38 +523,55 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_col_H(const float2* __rest
     const int nky = tp->nky, nkx = tp->nkx, ty = tp->ty;
     const int nterm = nky * nkx;
     float2* sw = lds + wave * (C::LwC * C::LSC + kLinePad);
-    float2 acc[kV], sp[kV];
+    float2 acc[kV];
 #pragma unroll
     for (int s = 0; s < kV; ++s) acc[s] = make_float2(0.f, 0.f);
-    // terms kx-major; Z_kx is re-read for every ky (it stays in L2)
-    for (int term = 0; term < nterm; ++term) {
-        const int kx = term / nky, ky = term - kx * nky;
-        const float2* zt = Zk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)it.f0 * N;
-        const float* am = tentY + ((size_t)ty * kMaxK + ky) * N;
-        float2 v[kV];
+    // terms kx-major: the wave's columns of Z_kx are read once and kept in
+    // registers for all k_y terms of that k_x
+    for (int kx = 0; kx < nkx; ++kx) {
+        float2 z[kV];
         {
             const int ln = fresh_lane(lane);
-            const float2* __restrict__ zl = zt + slot_base<N>(ln, ls);
-            float a[kV];
-            load_tent_col<N>(a, am, ln);
+            const float2* __restrict__ zl =
+                Zk + ((size_t)t * kMaxK + kx) * C::SPEC + (size_t)it.f0 * N + slot_base<N>(ln, ls);
+#pragma unroll
+            for (int s = 0; s < kV; ++s) z[s] = zl[slot_const<N, nat_radix<N>()>(s)];
             if (special) {
 #pragma unroll
-                for (int s = 0; s < kV; ++s) {
-                    constexpr int R = nat_radix<N>();
-                    v[s] = cscale(col_in(zl[slot_const<N, R>(s)], mode), a[s]);
-                }
-            } else {
-#pragma unroll
-                for (int s = 0; s < kV; ++s) {
-                    constexpr int R = nat_radix<N>();
-                    v[s] = cscale(zl[slot_const<N, R>(s)], a[s]);
-                }
+                for (int s = 0; s < kV; ++s) z[s] = col_in(z[s], mode);
             }
         }
-        fft_passes<N, kFwd>(v, sw, tw, lane);
-        load_spec<N, WV>(sp, spec + (size_t)tp->spec[ky * kMaxK + kx] * C::NSPEC, it, fresh_lane(lane));
+        for (int ky = 0; ky < nky; ++ky) {
+            float2 v[kV];
+            {
+                float a[kV];
+                load_tent_col<N>(a, tentY + ((size_t)ty * kMaxK + ky) * N, fresh_lane(lane));
 #pragma unroll
-        for (int s = 0; s < kV; ++s) acc[s] = cadd(acc[s], cmul(sp[s], v[s]));
+                for (int s = 0; s < kV; ++s) v[s] = cscale(z[s], a[s]);
+            }
+            fft_passes<N, kFwd>(v, sw, tw, lane);
+            // the spectrum in two halves, so that Z, v, acc and the
+            // spectrum values fit the register budget together
+            constexpr int RL = last_radix<N, kFwd>();
+            const int c0 = it.nyq ? N / 2 : it.f0;
+            const float2* __restrict__ bl = spec + (size_t)tp->spec[ky * kMaxK + kx] * C::NSPEC + (size_t)c0 * N +
+                                            slot_base<N>(fresh_lane(lane), ls);
+            {
+                float2 h[kV / 2];
+#pragma unroll
+                for (int s = 0; s < kV / 2; ++s) h[s] = bl[slot_const<N, RL>(s)];
+#pragma unroll
+                for (int s = 0; s < kV / 2; ++s) acc[s] = cadd(acc[s], cmul(h[s], v[s]));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                float2 h[kV / 2];
+#pragma unroll
+                for (int s = 0; s < kV / 2; ++s) h[s] = bl[slot_const<N, RL>(kV / 2 + s)];
+#pragma unroll
+                for (int s = 0; s < kV / 2; ++s) acc[kV / 2 + s] = cadd(acc[kV / 2 + s], cmul(h[s], v[kV / 2 + s]));
+            }
+        }
     }
     fft_passes<N, kInv>(acc, sw, tw + C::TWC_F, lane);
     float2* __restrict__ yl = Yc + (size_t)t * C::SPEC + (size_t)it.f0 * N + slot_base<N>(lane, ls);
