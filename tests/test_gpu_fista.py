@@ -9,7 +9,7 @@ from tests.test_gpu_solver import _f32, _mid_problem, small_workload_problem
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("reg,bc", [("tv", "neumann"), ("huber", "circular")])
+@pytest.mark.parametrize("reg,bc", [("tv", "neumann"), ("huber", "circular"), ("huber", "neumann")])
 def test_fista_inner_steps_match_oracle(reg, bc):
     from tests._gpu import context_of, rel_l2, to_dev
     prob = _mid_problem(reg, bc, seed=11)

@@ -55,7 +55,8 @@ def test_step_sizes_match_oracle():
 
 
 @pytest.mark.parametrize("reg,bc,model", [("tv", "neumann", "interp"), ("huber", "circular", "interp"),
-                                          ("tv", "neumann", "local")])
+                                          ("tv", "neumann", "local"), ("huber", "neumann", "interp"),
+                                          ("tv", "circular", "interp")])
 def test_inner_steps_match_oracle(reg, bc, model):
     from tests._gpu import context_of, rel_l2, to_dev
     prob = _mid_problem(reg, bc, model, seed=1)
