@@ -1008,89 +1008,112 @@ __global__ __launch_bounds__((Cfg<N, WV>::NT)) void k_row_update(
             };
             if (P.reg == 0) strips(IntC<0>{});
             else strips(IntC<1>{});
-        } else
-        // Circular differences: one thread per (column, kSeg rows), x at
-        // c - 1, c, c + 1 loaded per row.  Two tasks per step: their loads
-        // are issued together.
-        for (int t2 = 0; t2 < TASKS; t2 += 2) {
-            float X[2][kSeg + 2][3];
-            float U[2][kSeg];
-            int cc[2], iaa[2], cll[2], crr[2];
-            bool act[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                act[h] = t2 + h < TASKS;
-                const int task = tid + (t2 + h) * C::NT;
-                const int c = task % N;
-                const int ia = i0 + (task / N) * kSeg;
-                const bool colin = act[h] && c < sx;
-                cc[h] = c;
-                iaa[h] = ia;
-                cll[h] = c >= 1 ? c - 1 : (circ ? sx - 1 : -1);
-                crr[h] = c + 1 < sx ? c + 1 : (circ ? 0 : -1);
-#pragma unroll
-                for (int j = 0; j < kSeg + 2; ++j) {
-                    int rr = ia - 1 + j;
-                    if (rr < 0) rr = circ ? sy - 1 : -1;
-                    else if (rr >= sy) rr = (circ && rr == sy) ? 0 : -1;
-                    const bool ok = colin && rr >= 0;
-                    const float* rowp = xt + (size_t)(ok ? rr : 0) * N;
-                    X[h][j][0] = (ok && cll[h] >= 0) ? rowp[cll[h]] : 0.f;
-                    X[h][j][1] = ok ? rowp[c] : 0.f;
-                    X[h][j][2] = (ok && crr[h] >= 0) ? rowp[crr[h]] : 0.f;
-                }
-#pragma unroll
-                for (int k = 0; k < kSeg; ++k) {
-                    const int i = ia + k;
-                    U[h][k] = (colin && i < sy) ? ut[(size_t)i * N + c] : 0.f;
-                }
-            }
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (!act[h]) continue;
-                const int c = cc[h], ia = iaa[h], cl = cll[h], cr = crr[h];
-                const bool colin = c < sx;
-                const float oxc = colin ? ox[c] : 0.f;
-                // vertical term of the row above the segment: qv(ia-1, c)
-                float qv_up = 0.f;
-                if (colin && (ia >= 1 || circ) && ia < sy) {
-                    const float gh = cr >= 0 ? X[h][0][2] - X[h][0][1] : 0.f;
-                    const float gv = X[h][1][1] - X[h][0][1];
-                    qv_up = reg_scale(gh, gv, P) * gv;
-                }
-#pragma unroll
-                for (int k = 0; k < kSeg; ++k) {
-                    const int i = ia + k;
-                    float val = 0.f;
-                    if (colin && i < sy) {
-                        const bool nxt = (i + 1 < sy) || circ;
-                        const float xm = X[h][k + 1][1];
-                        const float gh = cr >= 0 ? X[h][k + 1][2] - xm : 0.f;
-                        const float gv = nxt ? X[h][k + 2][1] - xm : 0.f;
-                        const float sc = reg_scale(gh, gv, P);
-                        float g = qv_up - sc * (gh + gv);
-                        if (cl >= 0) {
-                            const float xl = X[h][k + 1][0];
-                            const float ghl = xm - xl;   // column c is the right neighbour of c-1
-                            const float gvl = nxt ? X[h][k + 2][0] - xl : 0.f;
-                            g += reg_scale(ghl, gvl, P) * ghl;
+        } else {
+            // Circular differences (this branch runs only for them): one thread
+            // per (column, kSeg rows), x at c - 1, c and c + 1 (wrapping around
+            // the support) per row.  Two tasks per step.  All their loads, with
+            // omega_x, omega_y and (FISTA) w_{j-1}, are issued together and
+            // unconditionally (every index lies in the frame), and a value
+            // outside the support is replaced by 0 where it is used, so the
+            // update issues no global load of its own (a wait for one would
+            // drain every load issued before it).
+            constexpr int UN = FISTA ? 2 * kSeg : kSeg;   // u, then (FISTA) w_{j-1}
+            auto circ_strips = [&](auto regc) {
+                constexpr int REG = decltype(regc)::value;
+                for (int t2 = 0; t2 < TASKS; t2 += 2) {
+                    float X[2][kSeg + 2][3];
+                    float U[2][UN], OY[2][kSeg], OX[2];
+                    int cc[2], iaa[2];
+                    bool act[2];
+    #pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        act[h] = t2 + h < TASKS;
+                        // an inactive slot loads the last task again (unused)
+                        const int task = tid + min(t2 + h, TASKS - 1) * C::NT;
+                        const int c = task % N;
+                        const int ia = i0 + (task / N) * kSeg;
+                        cc[h] = c;
+                        iaa[h] = ia;
+                        const int cl = c >= 1 ? c - 1 : sx - 1, cr = c + 1 < sx ? c + 1 : 0;
+    #pragma unroll
+                        for (int j = 0; j < kSeg + 2; ++j) {
+                            int rr = ia - 1 + j;
+                            if (rr < 0) rr = sy - 1;
+                            else if (rr >= sy) rr = 0;   // row sy wraps to 0; rows past it are masked
+                            const float* rowp = xt + (size_t)rr * N;
+                            X[h][j][0] = rowp[cl];
+                            X[h][j][1] = rowp[c];
+                            X[h][j][2] = rowp[cr];
                         }
-                        qv_up = sc * gv;
-                        const float alpha = P.gamma * oy[i] * oxc;
-                        const float grad = sg[(i - i0) * N + c] + P.lambda * g + alpha * (xm - U[h][k]);
-                        val = xm - tt * grad;
-                        if (P.positivity) val = project_nonneg(val);
+    #pragma unroll
+                        for (int k = 0; k < kSeg; ++k) U[h][k] = ut[(size_t)(ia + k) * N + c];
+                        if constexpr (FISTA) {
+    #pragma unroll
+                            for (int k = 0; k < kSeg; ++k) U[h][kSeg + k] = wt[(size_t)(ia + k) * N + c];
+                        }
+                        OX[h] = ox[c];
+    #pragma unroll
+                        for (int k = 0; k < kSeg; ++k) OY[h][k] = oy[ia + k];
                     }
-                    float xv = val;
-                    if constexpr (FISTA) {
-                        const float wp = wt[(size_t)i * N + c];   // 0 outside the support
-                        wt[(size_t)i * N + c] = val;
-                        if (beta != 0.f) xv = val + beta * (val - wp);
+    #pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        if (!act[h]) continue;
+                        const int c = cc[h], ia = iaa[h];
+                        const bool colin = c < sx;
+                        // the loaded rows, 0 where the row lies outside the support
+                        // (rows past the wrapped row sy) or the column does
+                        float Xv[kSeg + 2][3];
+    #pragma unroll
+                        for (int j = 0; j < kSeg + 2; ++j) {
+                            const int rr = ia - 1 + j;
+                            const bool ok = colin && rr <= sy;
+    #pragma unroll
+                            for (int m = 0; m < 3; ++m) Xv[j][m] = ok ? X[h][j][m] : 0.f;
+                        }
+                        const float oxc = colin ? OX[h] : 0.f;
+                        // vertical term of the row above the segment: qv(ia-1, c)
+                        float qv_up = 0.f;
+                        if (colin && ia < sy) {
+                            const float gh = Xv[0][2] - Xv[0][1];
+                            const float gv = Xv[1][1] - Xv[0][1];
+                            qv_up = reg_scale_k<REG>(gh, gv, P.reg_param) * gv;
+                        }
+    #pragma unroll
+                        for (int k = 0; k < kSeg; ++k) {
+                            const int i = ia + k;
+                            float val = 0.f;
+                            if (colin && i < sy) {
+                                const float xm = Xv[k + 1][1];
+                                const float gh = Xv[k + 1][2] - xm;
+                                const float gv = Xv[k + 2][1] - xm;
+                                const float sc = reg_scale_k<REG>(gh, gv, P.reg_param);
+                                float g = qv_up - sc * (gh + gv);
+                                {
+                                    const float xl = Xv[k + 1][0];
+                                    const float ghl = xm - xl;   // column c is the right neighbour of c-1
+                                    const float gvl = Xv[k + 2][0] - xl;
+                                    g += reg_scale_k<REG>(ghl, gvl, P.reg_param) * ghl;
+                                }
+                                qv_up = sc * gv;
+                                const float alpha = P.gamma * OY[h][k] * oxc;
+                                const float grad = sg[(i - i0) * N + c] + P.lambda * g + alpha * (xm - U[h][k]);
+                                val = xm - tt * grad;
+                                if (P.positivity) val = project_nonneg(val);
+                            }
+                            float xv = val;
+                            if constexpr (FISTA) {
+                                const float wp = U[h][kSeg + k];   // w_{j-1}: 0 outside the support
+                                wt[(size_t)i * N + c] = val;
+                                if (beta != 0.f) xv = val + beta * (val - wp);
+                            }
+                            xo[(size_t)i * N + c] = xv;
+                            sg[(i - i0) * N + c] = xv;
+                        }
                     }
-                    xo[(size_t)i * N + c] = xv;
-                    sg[(i - i0) * N + c] = xv;
                 }
-            }
+            };
+            if (P.reg == 0) circ_strips(IntC<0>{});
+            else circ_strips(IntC<1>{});
         }
         __syncthreads();
     }
