@@ -69,3 +69,16 @@ def test_measured_traffic_needs_matching_sources_and_launch_shape(tmp_path, monk
 def test_parse_plan(text, want):
     p = bench.parse_plan(text)
     assert (p.frame, p.col_waves, p.row_waves, p.tile_order, p.tile_groups) == want
+
+
+def test_more_than_one_gpu_is_refused_before_any_work():
+    """The solver runs all tiles on one GPU: --gpus N > 1 exits with status 2
+    and a JSON error line, before torch or the library is touched."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], cwd=root,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
